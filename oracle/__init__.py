@@ -1,0 +1,284 @@
+"""FP64 CPU oracle for the local FusedMM path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library and its Python binding
+never import it, and it imports nothing from them.
+
+The loops live in ``fmm_oracle.c`` (plain double-precision definitions of SDDMM,
+SpMMA, SpMMB and the CSR->CSC transpose).  This module assembles the paper's
+composite operations from them, exactly as the paper defines them (Section II):
+
+    FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B)
+    FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A)
+
+and the adjoints, which the paper does not give.  They are derived here from
+R = S * P with P = A B^T (the derivation is repeated in each docstring).
+
+Every input is promoted exactly to float64 before use.  A "pattern" argument is
+any object with attributes ``m, n, rowptr, colidx, val`` (canonical CSR).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from types import SimpleNamespace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fmm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+
+def build(force: bool = False) -> str:
+    """Compile fmm_oracle.c into liboracle.so with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                               "-std=c11", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            i64, p = ctypes.c_int64, ctypes.c_void_p
+            lib.oracle_sddmm.argtypes = [i64, i64, p, p, p, p, p, p, p, i64]
+            lib.oracle_spmm_a.argtypes = [i64, i64, p, p, p, p, p, p, i64]
+            lib.oracle_spmm_b.argtypes = [i64, i64, i64, p, p, p, p, p]
+            lib.oracle_csr_to_csc.argtypes = [i64, i64, p, p, p, p, p, p, p]
+            lib.oracle_num_threads.restype = ctypes.c_int
+            for f in ("oracle_sddmm", "oracle_spmm_a", "oracle_spmm_b", "oracle_csr_to_csc"):
+                getattr(lib, f).restype = None
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+
+def _rows(rows):
+    return None if rows is None else np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------------
+# The three primitives (Section II) and the transpose (Section IV-B)
+# ----------------------------------------------------------------------------------
+
+def sddmm(S, A, B, val="S", rows=None, out=None):
+    """R[p] = val[p] * <A_i:, B_j:> at each stored entry p = (i, j) (Eq. (1)).
+
+    ``val="S"`` uses S's values, ``val=None`` the pattern alone (all ones), or an
+    explicit array.  With ``rows`` only those rows' entries are computed (others 0).
+    """
+    lib = _load()
+    A, B = _f64(A), _f64(B)
+    r = A.shape[1]
+    assert A.shape == (S.m, r) and B.shape == (S.n, r)
+    v = _f64(S.val) if isinstance(val, str) else (None if val is None else _f64(val))
+    R = np.zeros(S.colidx.shape[0], dtype=np.float64) if out is None else out
+    rp, ci, rw = _i32(S.rowptr), _i32(S.colidx), _rows(rows)
+    lib.oracle_sddmm(S.m, r, _ptr(rp), _ptr(ci), _ptr(v), _ptr(A), _ptr(B), _ptr(R),
+                     _ptr(rw), 0 if rw is None else rw.shape[0])
+    return R
+
+
+def spmm_a(S, w, B, rows=None):
+    """SpMMA: C = W . B where W has S's pattern and stored values ``w`` (Section II)."""
+    lib = _load()
+    B, w = _f64(B), _f64(w)
+    r = B.shape[1]
+    assert B.shape[0] == S.n and w.shape[0] == S.colidx.shape[0]
+    rw = _rows(rows)
+    cnt = S.m if rw is None else rw.shape[0]
+    C = np.empty((cnt, r), dtype=np.float64)
+    rp, ci = _i32(S.rowptr), _i32(S.colidx)
+    lib.oracle_spmm_a(S.m, r, _ptr(rp), _ptr(ci), _ptr(w), _ptr(B), _ptr(C),
+                      _ptr(rw), 0 if rw is None else rw.shape[0])
+    return C
+
+
+def spmm_b(S, w, A):
+    """SpMMB: C' = W^T . A (n x r), W with S's pattern and stored values ``w`` (Section II)."""
+    lib = _load()
+    A, w = _f64(A), _f64(w)
+    r = A.shape[1]
+    assert A.shape[0] == S.m and w.shape[0] == S.colidx.shape[0]
+    C = np.empty((S.n, r), dtype=np.float64)
+    rp, ci = _i32(S.rowptr), _i32(S.colidx)
+    lib.oracle_spmm_b(S.m, S.n, r, _ptr(rp), _ptr(ci), _ptr(w), _ptr(A), _ptr(C))
+    return C
+
+
+def csr_to_csc(S):
+    """Stored transposed copy of S (Section IV-B): (colptr, rowidx, valT, perm),
+    rows ascending inside each column, perm[q] = CSR position of CSC entry q.
+    valT keeps the dtype of S.val."""
+    lib = _load()
+    nnz = S.colidx.shape[0]
+    colptr = np.empty(S.n + 1, dtype=np.int32)
+    rowidx = np.empty(nnz, dtype=np.int32)
+    perm = np.empty(nnz, dtype=np.int32)
+    v = _f64(S.val)
+    valT = np.empty(nnz, dtype=np.float64)
+    rp, ci = _i32(S.rowptr), _i32(S.colidx)
+    lib.oracle_csr_to_csc(S.m, S.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(colptr), _ptr(rowidx),
+                          _ptr(valT), _ptr(perm))
+    return colptr, rowidx, valT.astype(np.asarray(S.val).dtype), perm
+
+
+def transpose(S):
+    """S^T as a pattern object (n x m CSR), built from :func:`csr_to_csc`."""
+    colptr, rowidx, valT, perm = csr_to_csc(S)
+    return SimpleNamespace(m=S.n, n=S.m, rowptr=colptr, colidx=rowidx, val=valT, perm=perm)
+
+
+def absolute(S):
+    """|S|: same pattern, absolute stored values (for magnitude companions)."""
+    return SimpleNamespace(m=S.m, n=S.n, rowptr=S.rowptr, colidx=S.colidx,
+                           val=np.abs(_f64(S.val)))
+
+
+# ----------------------------------------------------------------------------------
+# Composite operations (Section II) and their adjoints
+# ----------------------------------------------------------------------------------
+
+def fusedmm_a(S, A, B, rows=None):
+    """FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B); m x r (or the listed rows)."""
+    R = sddmm(S, A, B, rows=rows)
+    return spmm_a(S, R, B, rows=rows)
+
+
+def fusedmm_b(S, A, B):
+    """FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A); n x r."""
+    R = sddmm(S, A, B)
+    return spmm_b(S, R, A)
+
+
+def fusedmm_a_backward(S, A, B, dC):
+    """Adjoint of C = FusedMMA(S, A, B) = R B with R = S * (A B^T), S's values fixed.
+
+    With upstream gradient dC (m x r): dL/dR_ij = <dC_i:, B_j:>, so the gradient
+    reaching P = A B^T is dP = S * (dC B^T) = SDDMM(dC, B, S).  Then
+      dA = dP B                         = SpMMA(dP, B)
+      dB = dP^T A + R^T dC              = SpMMB(dP, A) + SpMMB(R, dC)
+    (B enters twice: through the sampled product and as the SpMM operand).
+    Returns (dA, dB).
+    """
+    R = sddmm(S, A, B)
+    dP = sddmm(S, dC, B)
+    dA = spmm_a(S, dP, B)
+    dB = spmm_b(S, dP, A) + spmm_b(S, R, dC)
+    return dA, dB
+
+
+def fusedmm_b_backward(S, A, B, dC):
+    """Adjoint of C' = FusedMMB(S, A, B) = R^T A with R = S * (A B^T).
+
+    With upstream gradient dC (n x r): dL/dR_ij = <A_i:, dC_j:>, so
+    dP = S * (A dC^T) = SDDMM(A, dC, S), and
+      dA = dP B + R dC                  = SpMMA(dP, B) + SpMMA(R, dC)
+      dB = dP^T A                       = SpMMB(dP, A)
+    Returns (dA, dB).
+    """
+    R = sddmm(S, A, B)
+    dP = sddmm(S, A, dC)
+    dA = spmm_a(S, dP, B) + spmm_a(S, R, dC)
+    dB = spmm_b(S, dP, A)
+    return dA, dB
+
+
+def sddmm_backward(S, A, B, dR):
+    """Adjoint of R = SDDMM(A, B, S) (stored values R[p]) w.r.t. A and B:
+    dA = (S * dR) B = SpMMA(S*dR, B), dB = (S * dR)^T A = SpMMB(S*dR, A)."""
+    w = _f64(S.val) * _f64(dR)
+    return spmm_a(S, w, B), spmm_b(S, w, A)
+
+
+def spmm_a_backward(S, w, B, dC):
+    """Adjoint of C = W B (W: S's pattern with stored values w):
+    dw[p] = <dC_i:, B_j:> (an SDDMM with unit values), dB = W^T dC = SpMMB(w, dC)."""
+    return sddmm(S, dC, B, val=None), spmm_b(S, w, dC)
+
+
+def spmm_b_backward(S, w, A, dC):
+    """Adjoint of C' = W^T A: dw[p] = <A_i:, dC_j:>, dA = W dC' = SpMMA(w, dC')."""
+    return sddmm(S, A, dC, val=None), spmm_a(S, w, dC)
+
+
+# ----------------------------------------------------------------------------------
+# Row- and column-sampled forms for large inputs (rows are independent)
+# ----------------------------------------------------------------------------------
+
+def fusedmm_a_rows(S, A, B, rows):
+    """Rows ``rows`` of FusedMMA(S, A, B)."""
+    return fusedmm_a(S, A, B, rows=rows)
+
+
+def fusedmm_b_cols(ST, A, B, cols):
+    """Columns ``cols`` of FusedMMB(S, A, B), given ST = transpose(S):
+    FusedMMB(S, A, B)_j = sum_i S_ij <A_i, B_j> A_i = FusedMMA(S^T, B, A)_j."""
+    return fusedmm_a(ST, B, A, rows=cols)
+
+
+def fusedmm_a_backward_sampled(S, ST, A, B, dC, rows, cols):
+    """Rows ``rows`` of dA and rows ``cols`` of dB for the FusedMMA adjoint.
+    dA_i = sum_j dP_ij B_j (row form); dB_j = sum_i S_ij(<dC_i,B_j> A_i + <A_i,B_j> dC_i),
+    computed on S^T as SpMMA(S^T * (B dC^T), A) + SpMMA(S^T * (B A^T), dC)."""
+    dP = sddmm(S, dC, B, rows=rows)
+    dA = spmm_a(S, dP, B, rows=rows)
+    dPT = sddmm(ST, B, dC, rows=cols)
+    RT = sddmm(ST, B, A, rows=cols)
+    dB = spmm_a(ST, dPT, A, rows=cols) + spmm_a(ST, RT, dC, rows=cols)
+    return dA, dB
+
+
+def fusedmm_b_backward_sampled(S, ST, A, B, dC, rows, cols):
+    """Rows ``rows`` of dA and rows ``cols`` of dB for the FusedMMB adjoint (dC is n x r).
+    dA_i = sum_j S_ij(<A_i,dC_j> B_j + <A_i,B_j> dC_j); dB_j = sum_i S_ij <A_i,dC_j> A_i."""
+    dP = sddmm(S, A, dC, rows=rows)
+    R = sddmm(S, A, B, rows=rows)
+    dA = spmm_a(S, dP, B, rows=rows) + spmm_a(S, R, dC, rows=rows)
+    dPT = sddmm(ST, dC, A, rows=cols)
+    dB = spmm_a(ST, dPT, A, rows=cols)
+    return dA, dB
+
+
+# ----------------------------------------------------------------------------------
+# bfloat16 storage rounding (round to nearest, ties to even)
+# ----------------------------------------------------------------------------------
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even) and return them
+    as float32.  bfloat16 keeps the top 16 bits of an IEEE binary32; the discarded
+    low half decides the rounding.  NaNs stay NaN."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = x.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    rounded = ((u + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
+    out = rounded.view(np.float32).copy()
+    nan = np.isnan(x)
+    out[nan] = x[nan]
+    return out
