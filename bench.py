@@ -1,0 +1,245 @@
+"""Benchmark: fused FusedMMA forward + adjoint on one MI355X.
+
+One step = C = FusedMMA(S, A, B) (fused), then the adjoint for the loss sum(C * G):
+dA (row pass over the CSR) and dB (column pass over the stored transpose).  Inputs
+are seeded synthetic data resident in HBM before timing starts.  The default
+workload is Erdos-Renyi S 2^20 x 2^20 with 32 nonzeros per row, r = 128, float32.
+
+Prints one JSON line with the step throughput (GFLOP/s, counting 12 r nnz flops per
+step as the paper counts SDDMM and SpMM at 2 r nnz each), the roofline entry of the
+dominant kernel (timed with HIP events on the launch stream), side measurements
+(unfused float32 and fused bfloat16 steps, FusedMMB) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FusedMM fwd+bwd GFLOP/s and % HBM peak; fused/BF16 vs unfused FP32 at tol"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, m, n, nnz, r, e):
+    """Algorithmic HBM bytes of one launch under the gather model (every stored
+    entry fetches its dense row; index arrays, held rows and outputs move once)."""
+    if kind == "fwd":        # FusedMMA: rowptr, colidx+val, A, gathered B, C
+        return 4 * (m + 1) + 8 * nnz + e * m * r + e * r * nnz + 4 * m * r
+    if kind == "bwd_row":    # dA = FusedMMA(S, dC, B): rowptr, colidx+val, dC, gathered B, dA
+        return 4 * (m + 1) + 8 * nnz + 4 * m * r + e * r * nnz + 4 * m * r
+    if kind == "bwd_col":    # dB: colptr, rowidx+valT, B, gathered A and dC, dB
+        return 4 * (n + 1) + 8 * nnz + e * n * r + (e + 4) * r * nnz + 4 * n * r
+    raise ValueError(kind)
+
+
+def kernel_bytes_min(kind, m, n, nnz, r, e):
+    """Compulsory bytes: every array once (no re-fetch of gathered rows)."""
+    if kind == "fwd":
+        return 4 * (m + 1) + 8 * nnz + e * m * r + e * n * r + 4 * m * r
+    if kind == "bwd_row":
+        return 4 * (m + 1) + 8 * nnz + 4 * m * r + e * n * r + 4 * m * r
+    if kind == "bwd_col":
+        return 4 * (n + 1) + 8 * nnz + e * n * r + (e + 4) * m * r + 4 * n * r
+    raise ValueError(kind)
+
+
+def cpu_baseline(w, target_s=12.0):
+    """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload."""
+    from types import SimpleNamespace
+
+    import oracle
+
+    S = w["S"]
+    r = w["r"]
+    A = np.ascontiguousarray(w["A"], dtype=np.float64)
+    B = np.ascontiguousarray(w["B"], dtype=np.float64)
+    G = np.ascontiguousarray(w["G"], dtype=np.float64)
+
+    def run(K):
+        nz = int(S.rowptr[K])
+        Sk = SimpleNamespace(m=K, n=S.n, rowptr=S.rowptr[:K + 1], colidx=S.colidx[:nz],
+                             val=np.ascontiguousarray(S.val[:nz], dtype=np.float64))
+        t0 = time.perf_counter()
+        oracle.fusedmm_a(Sk, A[:K], B)
+        oracle.fusedmm_a_backward(Sk, A[:K], B, G[:K])
+        return time.perf_counter() - t0, nz
+
+    K0 = min(S.m, 8192)
+    t0, _ = run(K0)
+    K = int(min(S.m, max(K0, K0 * target_s / max(t0, 1e-3))))
+    t, nz = run(K)
+    gflops = 12.0 * r * nz / t / 1e9
+    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {K} of {S.m} rows ({nz} nonzeros), FusedMMA forward + adjoint in float64, "
+                      f"{t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="er1m_d32_r128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2203_07673_amd as F
+    from workloads import workload
+
+    t_gen = time.perf_counter()
+    w = workload(args.workload)
+    S, r = w["S"], w["r"]
+    m, n, nnz = S.m, S.n, S.nnz
+    log(f"generated {args.workload}: m={m} n={n} nnz={nnz} r={r} in {time.perf_counter() - t_gen:.1f}s")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_prep = time.perf_counter()
+    P = F.Pattern.from_csr(S, device=dev)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t_prep
+    log(f"pattern prep (validate + transpose + schedule) {prep_s:.2f}s; "
+        f"schedules csr={P.schedules['csr'] is not None} csc={P.schedules['csc'] is not None}")
+    A = torch.from_numpy(w["A"]).to(dev)
+    B = torch.from_numpy(w["B"]).to(dev)
+    G = torch.from_numpy(w["G"]).to(dev)
+    C = torch.empty(m, r, dtype=torch.float32, device=dev)
+    dA = torch.empty(m, r, dtype=torch.float32, device=dev)
+    dB = torch.empty(n, r, dtype=torch.float32, device=dev)
+
+    kinds = ("fwd", "bwd_row", "bwd_col")
+
+    def make_step(Ai, Bi, fused=True, R_ws=None, dP_ws=None):
+        def step(ev=None):
+            if ev is not None:
+                ev[0].record()
+            F.fusedmm_a_raw(P, Ai, Bi, out=C, fused=fused, R_ws=R_ws)
+            if ev is not None:
+                ev[1].record()
+            F.fusedmm_a_backward_raw(P, Ai, Bi, G, dA=dA, need=(True, False), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
+            if ev is not None:
+                ev[2].record()
+            F.fusedmm_a_backward_raw(P, Ai, Bi, G, dB=dB, need=(False, True), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
+            if ev is not None:
+                ev[3].record()
+        return step
+
+    def time_steps(step, steps, warmup, per_kernel=True):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)] if per_kernel else None
+        t0 = time.perf_counter()
+        for s in range(steps):
+            step(evs[s] if per_kernel else None)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        ktimes = None
+        if per_kernel:
+            ktimes = {k: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
+                      for i, k in enumerate(kinds)}
+        return t, ktimes
+
+    flops = 12.0 * r * nnz
+    step_f32 = make_step(A, B, fused=True)
+    log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
+    t_step, kt = time_steps(step_f32, args.steps, args.warmup)
+    gflops = flops / t_step / 1e9
+    log(f"fused f32 step {t_step * 1e3:.3f} ms -> {gflops:.1f} GFLOP/s; kernels (ms) {kt}")
+
+    e = 4
+    dom = max(kinds, key=lambda k: kt[k])
+    dom_bytes = kernel_bytes(dom, m, n, nnz, r, e)
+    achieved = dom_bytes / (kt[dom] * 1e-3) / 1e9
+    step_bytes = sum(kernel_bytes(k, m, n, nnz, r, e) for k in kinds)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": {"fwd": "FusedMMA forward (line_kernel op 3)",
+                           "bwd_row": "adjoint row pass dA (line_kernel op 3)",
+                           "bwd_col": "adjoint column pass dB (line_kernel op 4)"}[dom],
+                "kernel_ms": round(kt[dom], 4), "bytes_per_launch": int(dom_bytes),
+                "bytes_model": "gather (each stored entry fetches its dense row(s))",
+                "frac_compulsory_bytes": round(kernel_bytes_min(dom, m, n, nnz, r, e) / (kt[dom] * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 4)}
+
+    variants = {}
+    if not args.no_variants:
+        vsteps = max(3, args.steps // 4)
+        R_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        dP_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        t_unf, kt_unf = time_steps(make_step(A, B, fused=False, R_ws=R_ws, dP_ws=dP_ws), vsteps, 2)
+        variants["unfused_f32"] = {"ms_per_step": round(t_unf * 1e3, 4), "gflops": round(flops / t_unf / 1e9, 1),
+                                   "kernel_ms": {k: round(v, 4) for k, v in kt_unf.items()}}
+        log(f"unfused f32 step {t_unf * 1e3:.3f} ms")
+        del R_ws, dP_ws
+        A16, B16 = F.to_bf16(A), F.to_bf16(B)
+        t_bf, kt_bf = time_steps(make_step(A16, B16, fused=True), vsteps, 2)
+        variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
+                                  "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()}}
+        log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
+        variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
+        variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
+        del A16, B16
+        # FusedMMB forward, fused and unfused
+        Cb = torch.empty(n, r, dtype=torch.float32, device=dev)
+        Rb = torch.empty(nnz, dtype=torch.float32, device=dev)
+        for fused in (True, False):
+            for _ in range(2):
+                F.fusedmm_b_raw(P, A, B, out=Cb, fused=fused, R_ws=Rb)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(vsteps):
+                F.fusedmm_b_raw(P, A, B, out=Cb, fused=fused, R_ws=Rb)
+            e1.record()
+            torch.cuda.synchronize()
+            variants[f"fusedmm_b_fwd_{'fused' if fused else 'unfused'}_ms"] = round(e0.elapsed_time(e1) / vsteps, 4)
+        del Cb, Rb
+        variants["pattern_prep_s"] = round(prep_s, 3)
+        variants["step_bytes_gather_model"] = int(step_bytes)
+        variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "r": r, "storage": "f32",
+                   "step": "fused FusedMMA forward + adjoint (dA row pass, dB column pass)",
+                   "flops_per_step": flops},
+        "roofline": roofline,
+        "variants": variants,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

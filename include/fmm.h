@@ -1,0 +1,299 @@
+/*
+ * fmm.h -- C ABI of the local FusedMM library for AMD Instinct MI355X (gfx950).
+ *
+ * Operations (Bharadwaj, Buluc, Demmel, "Distributed-Memory Sparse Kernels for
+ * Machine Learning", Section II):
+ *
+ *   SDDMM(A, B, S)     = S * (A B^T)     Eq. (1): the sampled product, evaluated
+ *                                          only at the stored entries of S
+ *                                          (R_ij = S_ij <A_i:, B_j:>, Section IV-A)
+ *   SpMMA(S, B)        = S B             m x r output
+ *   SpMMB(S, A)        = S^T A           n x r output
+ *   FusedMMA(S, A, B)  = SpMMA(SDDMM(A, B, S), B)
+ *   FusedMMB(S, A, B)  = SpMMB(SDDMM(A, B, S), A)
+ *
+ * S is m x n sparse, A is m x r, B is n x r.  FusedMMB runs on a stored transposed
+ * copy of S (Section IV-B).  The fused calls keep each sampled value R_ij in
+ * registers between the two products instead of writing R to memory (the local
+ * fused kernel the paper cites in Section IV-B).  Backward calls give the adjoints
+ * with respect to A and B for a fixed S.
+ *
+ * Conventions that hold for every call unless its comment says otherwise:
+ *   * Pointers named in a call are DEVICE pointers; sizes and descriptors are host
+ *     values.  The caller owns every buffer.  Calls never allocate, except
+ *     fmm_validate (a 4-byte flag) and the batch-plan calls (their own tables).
+ *   * Dense matrices are row-major with r contiguous elements per row (row stride r).
+ *     FMM_F32 and FMM_BF16 name the storage of A and B; S values, dC and every
+ *     output are float32 for both.  FMM_F64 makes everything float64.
+ *     Limits on r: FMM_F32 r <= 1024 when r % 4 == 0, else r <= 256; FMM_BF16
+ *     r % 8 == 0 and r <= 1024; FMM_F64 r <= 512 when r is even, else r <= 256.
+ *     When r*sizeof(elem) is a multiple of 16 the dense bases must be 16-byte
+ *     aligned (FMM_ERR_UNSUPPORTED otherwise).
+ *   * Index arrays are int32 and canonical: ptr is non-decreasing with ptr[0] = 0,
+ *     ptr[major] = nnz; idx holds minor indices strictly increasing inside each
+ *     major line.  Hot calls trust this; fmm_validate checks it.
+ *   * Calls enqueue work on `stream` and return without waiting, except where a
+ *     comment says "synchronous".  An invalid argument returns a negative status
+ *     before anything is enqueued.  A failed HIP launch returns FMM_ERR_HIP and
+ *     fmm_last_hip_error() gives the hipError_t.
+ *   * beta: outputs are overwritten when beta == 0 (prior contents are not read),
+ *     otherwise out = beta * out + result (the "+=" form of the paper's local calls,
+ *     Algorithm 1).
+ *   * Results are deterministic: no floating-point atomics; every output element is
+ *     summed in a fixed order for a fixed pattern, schedule and r.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_ABI_VERSION 1
+
+typedef enum fmm_status {
+    FMM_OK = 0,
+    FMM_ERR_NULL = -1,          /* a required pointer is NULL                          */
+    FMM_ERR_DIM = -2,           /* a size is negative, zero where it must not be, or
+                                   inconsistent between arguments                       */
+    FMM_ERR_DTYPE = -3,         /* unknown dtype, or dtype / r combination unsupported  */
+    FMM_ERR_ORIENT = -4,        /* descriptor has the wrong orientation for the call    */
+    FMM_ERR_INDEX = -5,         /* fmm_validate: index out of range, or ptr not
+                                   monotone / not starting at 0 / not ending at nnz     */
+    FMM_ERR_NONCANONICAL = -6,  /* fmm_validate: duplicate or unsorted minor indices    */
+    FMM_ERR_WORKSPACE = -7,     /* workspace missing or smaller than required           */
+    FMM_ERR_UNSUPPORTED = -8,   /* valid request this build does not implement          */
+    FMM_ERR_HIP = -9            /* a HIP runtime call failed                           */
+} fmm_status;
+
+typedef enum fmm_dtype { FMM_F32 = 0, FMM_BF16 = 1, FMM_F64 = 2 } fmm_dtype;
+typedef enum fmm_orient { FMM_CSR = 0, FMM_CSC = 1 } fmm_orient;
+
+/* flags for the fused calls */
+#define FMM_FUSED 0    /* one pass, sampled values kept in registers                    */
+#define FMM_UNFUSED 1  /* SDDMM writes R (nnz values) to R_ws, then SpMM reads it back  */
+
+/*
+ * A sparse matrix S (rows x cols) in one orientation.
+ *   orient == FMM_CSR: major lines are rows, ptr = rowptr[rows+1], idx = colidx.
+ *   orient == FMM_CSC: major lines are columns, ptr = colptr[cols+1], idx = rowidx,
+ *                      val = S's values in CSC order, perm[q] = CSR position of the
+ *                      q-th CSC entry (needed only where a call says so).
+ * val is float32 (float64 for FMM_F64); NULL means every stored value is 1.
+ *
+ * Optional split schedule (from fmm_schedule_count / fmm_schedule_fill): major lines
+ * with more than long_len stored entries are cut into chunks that run in parallel and
+ * are summed afterwards in chunk order.  n_chunks == 0 disables it.
+ */
+typedef struct fmm_sparse {
+    int32_t orient;
+    int32_t rows, cols;
+    int32_t nnz;
+    const int32_t *ptr;
+    const int32_t *idx;
+    const void *val;
+    const int32_t *perm;
+    int32_t long_len;          /* lines with more entries than this are split            */
+    int32_t n_chunks;          /* number of chunk items                                  */
+    int32_t n_splits;          /* number of split lines                                  */
+    int32_t reserved;
+    const int32_t *chunks;     /* [3*n_chunks]: line, begin position, end position       */
+    const int32_t *splits;     /* [3*n_splits]: line, first chunk, chunk count           */
+} fmm_sparse;
+
+/* ---------------------------------------------------------------- diagnostics */
+
+int32_t fmm_abi_version(void);
+/* Static text for a status code. */
+const char *fmm_status_string(int32_t status);
+/* hipError_t of the last HIP failure seen by this thread (0 if none). */
+int32_t fmm_last_hip_error(void);
+/* Number of compute units and the GPU architecture name of the current device
+   (arch: caller buffer of arch_len bytes, NUL-terminated). Synchronous. */
+fmm_status fmm_device_info(int32_t *num_cu, char *arch, int32_t arch_len);
+
+/*
+ * Lane-group shape override for every later launch in this process (tuning and
+ * benchmarking): `lanes` lanes own one major line and each lane holds `nv` 16-byte
+ * vectors of an r-vector.  (0, 0) restores the automatic choice (the smallest power of
+ * two lanes covering r).  Compiled shapes: nv = 1 with lanes 1..64 (powers of two),
+ * nv = 2 with lanes 16, 32, 64, nv = 4 with lanes 64; a shape that does not fit r
+ * falls back to the automatic one.  Not synchronised with launches on other threads.
+ */
+fmm_status fmm_set_tuning(int32_t lanes, int32_t nv);
+
+/* ---------------------------------------------------------------- pattern prep */
+
+/*
+ * Check that S is canonical (see conventions): ptr[0] == 0, ptr[major] == nnz, ptr
+ * non-decreasing, 0 <= idx < minor extent, idx strictly increasing in each line.
+ * Synchronous.  Returns FMM_OK, FMM_ERR_INDEX or FMM_ERR_NONCANONICAL.  Allocates
+ * a 4-byte device flag for the duration of the call.
+ */
+fmm_status fmm_validate(const fmm_sparse *S, hipStream_t stream);
+
+/*
+ * Stored transposed copy of a CSR pattern (Section IV-B): from rowptr[m+1],
+ * colidx[nnz] (and optional values val[nnz] of dtype val_dtype: FMM_F32 or FMM_F64)
+ * build colptr[n+1], rowidx[nnz], perm[nnz] and, when val and valT are both
+ * non-NULL, valT[q] = val[perm[q]].  Rows inside a column come out ascending, so
+ * the result is the unique canonical CSC and equals any exact transpose bit for bit.
+ * Needs a device workspace of fmm_csr_to_csc_workspace() bytes.  nnz < 2^31.
+ */
+fmm_status fmm_csr_to_csc_workspace(int32_t m, int32_t n, int32_t nnz, size_t *bytes);
+fmm_status fmm_csr_to_csc(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
+                          const int32_t *colidx, const void *val, int32_t val_dtype,
+                          int32_t *colptr, int32_t *rowidx, void *valT, int32_t *perm,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Split schedule for skewed line lengths.  Lines (rows of a CSR, columns of a CSC)
+ * with more than long_len entries are cut into chunks of at most `chunk` entries.
+ *   fmm_schedule_count: synchronous; writes the number of chunks and of split lines
+ *                       to the host ints *n_chunks, *n_splits.
+ *   fmm_schedule_fill:  fills chunks[3*n_chunks] (line, begin, end) and
+ *                       splits[3*n_splits] (line, first chunk, chunk count), lines
+ *                       ascending.
+ * Both take a workspace of fmm_schedule_workspace() bytes.  long_len >= chunk >= 1.
+ */
+fmm_status fmm_schedule_workspace(int32_t nmajor, size_t *bytes);
+fmm_status fmm_schedule_count(const int32_t *ptr, int32_t nmajor, int32_t long_len, int32_t chunk,
+                              int32_t *n_chunks, int32_t *n_splits, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
+fmm_status fmm_schedule_fill(const int32_t *ptr, int32_t nmajor, int32_t long_len, int32_t chunk,
+                             int32_t *chunks, int32_t *splits, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Round float32 to bfloat16 storage (nearest, ties to even; NaN -> 0x7FC0). */
+fmm_status fmm_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t stream);
+
+/*
+ * Workspace bytes a call needs for the given descriptor(s), r and dtype: the split
+ * partial sums (n_chunks * r output elements for each descriptor the call walks).
+ * op: one of the FMM_OP_* values below.  Zero when no descriptor has a schedule.
+ */
+#define FMM_OP_SDDMM 0
+#define FMM_OP_SPMM_A 1
+#define FMM_OP_SPMM_B 2
+#define FMM_OP_FUSEDMM_A 3
+#define FMM_OP_FUSEDMM_B 4
+#define FMM_OP_FUSEDMM_A_BWD 5
+#define FMM_OP_FUSEDMM_B_BWD 6
+#define FMM_OP_SDDMM_BWD 7
+#define FMM_OP_SPMM_A_BWD 8
+#define FMM_OP_SPMM_B_BWD 9
+fmm_status fmm_workspace_size(int32_t op, const fmm_sparse *S_csr, const fmm_sparse *S_csc,
+                              int32_t r, int32_t dtype, size_t *bytes);
+
+/* ---------------------------------------------------------------- forward */
+
+/*
+ * SDDMM, Eq. (1): R[p] = beta*R[p] + val[p] * <A_i:, B_j:> for every stored entry
+ * p = (i, j) of S, in S's orientation order (CSR positions for a CSR descriptor,
+ * CSC positions for a CSC one).  A: rows x r, B: cols x r, R: nnz outputs.
+ */
+fmm_status fmm_sddmm(const fmm_sparse *S, const void *A, const void *B, int32_t r, int32_t dtype,
+                     void *R, double beta, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * SpMMA (Section II): C = beta*C + W B, C: rows x r, B: cols x r, where W has S's
+ * pattern and stored values w[p] (CSR order, output dtype), or S's own values when
+ * w is NULL.  S_csr must be a CSR descriptor.
+ */
+fmm_status fmm_spmm_a(const fmm_sparse *S_csr, const void *w, const void *B, int32_t r,
+                      int32_t dtype, void *C, double beta, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/*
+ * SpMMB (Section II): C = beta*C + W^T A, C: cols x r, A: rows x r.  S_csc must be a
+ * CSC descriptor.  W has S's pattern; its stored values are S's own (valT, CSC
+ * order) when w is NULL, else w indexed by CSC position when w_order == FMM_CSC, or
+ * by CSR position through perm when w_order == FMM_CSR (then S_csc->perm is required).
+ */
+fmm_status fmm_spmm_b(const fmm_sparse *S_csc, const void *w, int32_t w_order, const void *A,
+                      int32_t r, int32_t dtype, void *C, double beta, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/*
+ * FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B) (Section II; row form in Section IV-B):
+ * C_i: = sum_j S_ij <A_i:, B_j:> B_j:, C: rows x r, overwritten (beta = 0).
+ * flags FMM_FUSED: one pass.  FMM_UNFUSED: R_ws (nnz output elements) receives R,
+ * then a second pass reads it back.  ws: split partials (see fmm_workspace_size).
+ */
+fmm_status fmm_fusedmm_a(const fmm_sparse *S_csr, const void *A, const void *B, int32_t r,
+                         int32_t dtype, void *C, int32_t flags, void *R_ws, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/*
+ * FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A) (Section II):
+ * C'_j: = sum_i S_ij <A_i:, B_j:> A_i:, C': cols x r, computed on the CSC descriptor
+ * as FusedMMA(S^T, B, A) (Section IV-B's transposed copy).  UNFUSED: R_ws receives
+ * R in CSC order.
+ */
+fmm_status fmm_fusedmm_b(const fmm_sparse *S_csc, const void *A, const void *B, int32_t r,
+                         int32_t dtype, void *C, int32_t flags, void *R_ws, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- backward */
+
+/*
+ * Adjoint of C = FusedMMA(S, A, B) for fixed S, with upstream gradient dC (rows x r):
+ *   dP = S * (dC B^T)          (the gradient reaching A B^T, an SDDMM)
+ *   dA = dP B                  = FusedMMA(S, dC, B)            (row pass on S_csr)
+ *   dB = dP^T A + R^T dC       with R = S * (A B^T)            (column pass on S_csc)
+ * dA or dB may be NULL to skip that output.  FMM_FUSED recomputes the sampled values
+ * in registers; FMM_UNFUSED writes dP to dP_ws (nnz, CSR order) and needs R from the
+ * unfused forward in R_ws (CSR order) plus S_csc->perm.
+ */
+fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
+                                  const void *B, const void *dC, int32_t r, int32_t dtype,
+                                  void *dA, void *dB, int32_t flags, const void *R_ws, void *dP_ws,
+                                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of C' = FusedMMB(S, A, B) with upstream gradient dC (cols x r):
+ *   dP = S * (A dC^T)
+ *   dA = dP B + R dC           (row pass on S_csr)
+ *   dB = dP^T A                = FusedMMB(S, A, dC)            (column pass on S_csc)
+ * Same flag and workspace rules as fmm_fusedmm_a_backward (R_ws from the unfused
+ * FusedMMB forward is in CSC order; dP_ws is written in CSR order).
+ */
+fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
+                                  const void *B, const void *dC, int32_t r, int32_t dtype,
+                                  void *dA, void *dB, int32_t flags, const void *R_ws, void *dP_ws,
+                                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of R = SDDMM(A, B, S) with upstream gradient dR (nnz, CSR order):
+ *   dA = (S * dR) B on S_csr,  dB = (S * dR)^T A on S_csc (reads dR through perm).
+ */
+fmm_status fmm_sddmm_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
+                              const void *B, const void *dR, int32_t r, int32_t dtype, void *dA,
+                              void *dB, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of C = SpMMA with stored values w (CSR order; NULL = S's values):
+ *   dw[p] = <dC_i:, B_j:>        (nnz, CSR order; the gradient of the stored values)
+ *   dB    = W^T dC               on S_csc (reads w through perm)
+ */
+fmm_status fmm_spmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *w,
+                               const void *B, const void *dC, int32_t r, int32_t dtype, void *dw,
+                               void *dB, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of C' = SpMMB with stored values w (CSR order; NULL = S's values), dC': cols x r:
+ *   dw[p] = <A_i:, dC'_j:>       (nnz, CSR order)
+ *   dA    = W dC'                on S_csr
+ */
+fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *w,
+                               const void *A, const void *dC, int32_t r, int32_t dtype, void *dw,
+                               void *dA, void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

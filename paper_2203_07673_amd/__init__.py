@@ -1,0 +1,27 @@
+"""Local FusedMM (SDDMM -> SpMM) for AMD Instinct MI355X.
+
+The compute lives in libfmm.so (hand-written HIP for gfx950, C ABI in
+include/fmm.h); this package is its Python binding.
+"""
+from ._capi import FmmError, load as _load_library  # noqa: F401
+from .fusedmm import (  # noqa: F401
+    Pattern,
+    device_info,
+    dtype_code,
+    fusedmm_a,
+    fusedmm_a_backward_raw,
+    fusedmm_a_raw,
+    fusedmm_b,
+    fusedmm_b_backward_raw,
+    fusedmm_b_raw,
+    sddmm,
+    sddmm_raw,
+    set_tuning,
+    spmm_a,
+    spmm_a_raw,
+    spmm_b,
+    spmm_b_raw,
+    to_bf16,
+)
+
+__version__ = "0.1.0"

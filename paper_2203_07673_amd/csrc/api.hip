@@ -1,0 +1,743 @@
+// C ABI of the local FusedMM library: argument checks, workspace rules and the
+// mapping of every public call onto line-kernel launches.  See include/fmm.h for
+// the contract of each entry point.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "fmm.h"
+#include "fmm_internal.hpp"
+
+namespace fmm {
+
+static thread_local int32_t g_last_hip_error = 0;
+
+static Tuning g_tuning = {0, 0};
+Tuning &tuning() { return g_tuning; }
+
+static bool is_compiled_shape(int L, int NV)
+{
+    switch (NV) {
+    case 1: return L == 1 || L == 2 || L == 4 || L == 8 || L == 16 || L == 32 || L == 64;
+    case 2: return L == 16 || L == 32 || L == 64;
+    case 4: return L == 64;
+    default: return false;
+    }
+}
+
+bool shape_supported(Shape s, int r, int vw)
+{
+    if (!is_compiled_shape(s.L, s.NV)) return false;
+    const int C = r / vw;  // vectors per r-vector
+    return s.L * s.NV >= C;  // the group's vectors cover r (surplus lanes are masked)
+}
+
+Shape default_shape(int r, int vw)
+{
+    const int C = r / vw;
+    int L = 1;
+    while (L < C && L < 64) L <<= 1;
+    int NV = (C + L - 1) / L;
+    if (NV == 3) NV = 4;
+    return Shape{L, NV};
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+namespace {
+
+struct Kinds {
+    int path;      // PATH_*
+    size_t sbytes; // storage element size of A/B
+    size_t obytes; // element size of S values, dC and outputs
+};
+
+fmm_status kinds_for(int32_t dtype, int32_t r, Kinds *k)
+{
+    switch (dtype) {
+    case FMM_F32:
+        *k = Kinds{PATH_F32, 4, 4};
+        if (r < 1 || (r % 4 == 0 ? r > 1024 : r > 256)) return FMM_ERR_DTYPE;
+        return FMM_OK;
+    case FMM_BF16:
+        *k = Kinds{PATH_BF16, 2, 4};
+        if (r < 8 || r % 8 != 0 || r > 1024) return FMM_ERR_DTYPE;
+        return FMM_OK;
+    case FMM_F64:
+        *k = Kinds{PATH_F64, 8, 8};
+        if (r < 1 || (r % 2 == 0 ? r > 512 : r > 256)) return FMM_ERR_DTYPE;
+        return FMM_OK;
+    default:
+        return FMM_ERR_DTYPE;
+    }
+}
+
+fmm_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return FMM_OK;
+    g_last_hip_error = (int32_t)e;
+    return FMM_ERR_HIP;
+}
+
+// Vector loads need 16-byte aligned rows; rows are r elements apart.
+bool aligned_ok(const void *p, size_t elem, int32_t r)
+{
+    if (((size_t)r * elem) % 16 != 0) return true;  // scalar path
+    return ((uintptr_t)p % 16) == 0;
+}
+
+fmm_status check_sparse(const fmm_sparse *S, int orient)
+{
+    if (!S) return FMM_ERR_NULL;
+    if (S->orient != FMM_CSR && S->orient != FMM_CSC) return FMM_ERR_ORIENT;
+    if (orient >= 0 && S->orient != orient) return FMM_ERR_ORIENT;
+    if (S->rows < 0 || S->cols < 0 || S->nnz < 0) return FMM_ERR_DIM;
+    if (!S->ptr) return FMM_ERR_NULL;
+    if (S->nnz > 0 && !S->idx) return FMM_ERR_NULL;
+    if (S->n_chunks < 0 || S->n_splits < 0) return FMM_ERR_DIM;
+    if (S->n_chunks > 0) {
+        if (!S->chunks || !S->splits) return FMM_ERR_NULL;
+        if (S->long_len < 1 || S->n_splits < 1) return FMM_ERR_DIM;
+    }
+    return FMM_OK;
+}
+
+inline int32_t nmajor(const fmm_sparse *S) { return S->orient == FMM_CSR ? S->rows : S->cols; }
+inline int32_t nminor(const fmm_sparse *S) { return S->orient == FMM_CSR ? S->cols : S->rows; }
+
+size_t partial_bytes(const fmm_sparse *S, int32_t r, size_t obytes)
+{
+    return (S && S->n_chunks > 0) ? (size_t)S->n_chunks * (size_t)r * obytes : 0;
+}
+
+fmm_status check_ws(const fmm_sparse *S, int32_t r, size_t obytes, void *ws, size_t ws_bytes)
+{
+    const size_t need = partial_bytes(S, r, obytes);
+    if (need == 0) return FMM_OK;
+    if (!ws || ws_bytes < need) return FMM_ERR_WORKSPACE;
+    if ((uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    return FMM_OK;
+}
+
+LineArgs base_args(const fmm_sparse *S, int32_t r, void *ws)
+{
+    LineArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nlines = nmajor(S);
+    a.r = r;
+    a.ptr = S->ptr;
+    a.idx = S->idx;
+    a.val = S->val;
+    a.long_len = S->long_len;
+    a.n_chunks = S->n_chunks;
+    a.chunks = S->chunks;
+    a.partial = ws;
+    a.beta = 0.0;
+    return a;
+}
+
+Shape hint() { return Shape{tuning().lanes, tuning().nv}; }
+
+// Operand kinds of the bfloat16 path: 'S' = storage (bfloat16), 'O' = float32.
+template <int OP>
+hipError_t run(int path, char hk, char g1k, char g2k, const LineArgs &a, const fmm_sparse *S, hipStream_t st)
+{
+    const int32_t ns = S->n_chunks > 0 ? S->n_splits : 0;
+    const int32_t *sp = S->splits;
+    if (path == PATH_F32) return launch_lines<OP, float, float, float, float>(a, ns, sp, hint(), st);
+    if (path == PATH_F64) return launch_lines<OP, double, double, double, double>(a, ns, sp, hint(), st);
+    typedef bf16_t Sb;
+    typedef float Of;
+    if constexpr (OP == OP_SDDMM) {
+        if (hk == 'S' && g1k == 'S') return launch_lines<OP, Sb, Sb, Sb, float>(a, ns, sp, hint(), st);
+        if (hk == 'O' && g1k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
+        if (hk == 'S' && g1k == 'O') return launch_lines<OP, Sb, Of, Of, float>(a, ns, sp, hint(), st);
+    } else if constexpr (OP == OP_SPMM1) {
+        if (g1k == 'S') return launch_lines<OP, Sb, Sb, Sb, float>(a, ns, sp, hint(), st);
+        if (g1k == 'O') return launch_lines<OP, Of, Of, Of, float>(a, ns, sp, hint(), st);
+    } else if constexpr (OP == OP_SPMM2) {
+        if (g1k == 'S' && g2k == 'O') return launch_lines<OP, Sb, Sb, Of, float>(a, ns, sp, hint(), st);
+    } else if constexpr (OP == OP_FUSED1) {
+        if (hk == 'S' && g1k == 'S') return launch_lines<OP, Sb, Sb, Sb, float>(a, ns, sp, hint(), st);
+        if (hk == 'O' && g1k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
+    } else if constexpr (OP == OP_FUSED2) {
+        if (hk == 'S' && g1k == 'S' && g2k == 'O') return launch_lines<OP, Sb, Sb, Of, float>(a, ns, sp, hint(), st);
+    }
+    (void)g2k;
+    return hipErrorInvalidValue;
+}
+
+#define FMM_TRY(x)                                                                               \
+    do {                                                                                         \
+        fmm_status _s = (x);                                                                     \
+        if (_s != FMM_OK) return _s;                                                             \
+    } while (0)
+
+#define FMM_HIP(x)                                                                               \
+    do {                                                                                         \
+        hipError_t _e = (x);                                                                     \
+        if (_e != hipSuccess) return hip_status(_e);                                             \
+    } while (0)
+
+fmm_status check_dense(const void *p, int64_t rows, size_t elem, int32_t r)
+{
+    if (rows > 0 && !p) return FMM_ERR_NULL;
+    if (rows > 0 && !aligned_ok(p, elem, r)) return FMM_ERR_UNSUPPORTED;
+    return FMM_OK;
+}
+
+fmm_status check_pair(const fmm_sparse *S_csr, const fmm_sparse *S_csc)
+{
+    FMM_TRY(check_sparse(S_csr, FMM_CSR));
+    FMM_TRY(check_sparse(S_csc, FMM_CSC));
+    if (S_csr->rows != S_csc->rows || S_csr->cols != S_csc->cols || S_csr->nnz != S_csc->nnz) return FMM_ERR_DIM;
+    return FMM_OK;
+}
+
+size_t max_partial(const fmm_sparse *a, const fmm_sparse *b, int32_t r, size_t obytes)
+{
+    size_t x = partial_bytes(a, r, obytes), y = partial_bytes(b, r, obytes);
+    return x > y ? x : y;
+}
+
+fmm_status check_ws2(const fmm_sparse *a, const fmm_sparse *b, int32_t r, size_t obytes, void *ws, size_t ws_bytes)
+{
+    const size_t need = max_partial(a, b, r, obytes);
+    if (need == 0) return FMM_OK;
+    if (!ws || ws_bytes < need || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fmm_abi_version(void) { return FMM_ABI_VERSION; }
+
+const char *fmm_status_string(int32_t status)
+{
+    switch (status) {
+    case FMM_OK: return "ok";
+    case FMM_ERR_NULL: return "required pointer is NULL";
+    case FMM_ERR_DIM: return "invalid or inconsistent size";
+    case FMM_ERR_DTYPE: return "unsupported dtype or dtype/r combination";
+    case FMM_ERR_ORIENT: return "sparse descriptor has the wrong orientation";
+    case FMM_ERR_INDEX: return "index out of range or malformed pointer array";
+    case FMM_ERR_NONCANONICAL: return "minor indices not strictly increasing within a line";
+    case FMM_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case FMM_ERR_UNSUPPORTED: return "unsupported request (alignment or size limit)";
+    case FMM_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int32_t fmm_last_hip_error(void) { return g_last_hip_error; }
+
+fmm_status fmm_device_info(int32_t *num_cu, char *arch, int32_t arch_len)
+{
+    int dev = 0;
+    FMM_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    FMM_HIP(hipGetDeviceProperties(&prop, dev));
+    if (num_cu) *num_cu = prop.multiProcessorCount;
+    if (arch && arch_len > 0) {
+        strncpy(arch, prop.gcnArchName, (size_t)arch_len - 1);
+        arch[arch_len - 1] = 0;
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_set_tuning(int32_t lanes, int32_t nv)
+{
+    if (lanes < 0 || nv < 0) return FMM_ERR_DIM;
+    if ((lanes == 0) != (nv == 0)) return FMM_ERR_DIM;
+    if (lanes != 0 && !is_compiled_shape(lanes, nv)) return FMM_ERR_UNSUPPORTED;
+    tuning().lanes = lanes;
+    tuning().nv = nv;
+    return FMM_OK;
+}
+
+// ---------------------------------------------------------------- pattern prep
+
+fmm_status fmm_validate(const fmm_sparse *S, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S, -1));
+    int32_t *flag = nullptr;
+    FMM_HIP(hipMalloc(&flag, 4));
+    hipError_t e = hipMemsetAsync(flag, 0, 4, stream);
+    if (e == hipSuccess) e = validate(nmajor(S), nminor(S), S->nnz, S->ptr, S->idx, flag, stream);
+    int32_t f = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, flag, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipError_t e2 = hipFree(flag);
+    if (e != hipSuccess) return hip_status(e);
+    if (e2 != hipSuccess) return hip_status(e2);
+    if (f & 1) return FMM_ERR_INDEX;
+    if (f & 2) return FMM_ERR_NONCANONICAL;
+    return FMM_OK;
+}
+
+fmm_status fmm_csr_to_csc_workspace(int32_t m, int32_t n, int32_t nnz, size_t *bytes)
+{
+    if (!bytes) return FMM_ERR_NULL;
+    if (m < 0 || n < 0 || nnz < 0) return FMM_ERR_DIM;
+    *bytes = transpose_workspace_bytes(m, n, nnz);
+    return FMM_OK;
+}
+
+fmm_status fmm_csr_to_csc(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                          const void *val, int32_t val_dtype, int32_t *colptr, int32_t *rowidx, void *valT,
+                          int32_t *perm, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (m < 0 || n < 0 || nnz < 0) return FMM_ERR_DIM;
+    if (!rowptr || !colptr) return FMM_ERR_NULL;
+    if (nnz > 0 && (!colidx || !rowidx || !perm)) return FMM_ERR_NULL;
+    if (val && val_dtype != FMM_F32 && val_dtype != FMM_F64) return FMM_ERR_DTYPE;
+    if (nnz > 0 && m == 0) return FMM_ERR_DIM;
+    if (!ws || ws_bytes < transpose_workspace_bytes(m, n, nnz)) return FMM_ERR_WORKSPACE;
+    if ((uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    FMM_HIP(csr_to_csc(m, n, nnz, rowptr, colidx, val, val_dtype == FMM_F64 ? 8 : 4, colptr, rowidx, valT, perm, ws,
+                       stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_schedule_workspace(int32_t nmaj, size_t *bytes)
+{
+    if (!bytes) return FMM_ERR_NULL;
+    if (nmaj < 0) return FMM_ERR_DIM;
+    *bytes = schedule_workspace_bytes(nmaj);
+    return FMM_OK;
+}
+
+fmm_status fmm_schedule_count(const int32_t *ptr, int32_t nmaj, int32_t long_len, int32_t chunk, int32_t *n_chunks,
+                              int32_t *n_splits, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!ptr || !n_chunks || !n_splits) return FMM_ERR_NULL;
+    if (nmaj < 0 || chunk < 1 || long_len < chunk) return FMM_ERR_DIM;
+    if (!ws || ws_bytes < schedule_workspace_bytes(nmaj) || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    int32_t totals[2] = {0, 0};
+    FMM_HIP(schedule_count(ptr, nmaj, long_len, chunk, totals, ws, stream));
+    *n_chunks = totals[0];
+    *n_splits = totals[1];
+    return FMM_OK;
+}
+
+fmm_status fmm_schedule_fill(const int32_t *ptr, int32_t nmaj, int32_t long_len, int32_t chunk, int32_t *chunks,
+                             int32_t *splits, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!ptr || !chunks || !splits) return FMM_ERR_NULL;
+    if (nmaj < 0 || chunk < 1 || long_len < chunk) return FMM_ERR_DIM;
+    if (!ws || ws_bytes < schedule_workspace_bytes(nmaj) || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    FMM_HIP(schedule_fill(ptr, nmaj, long_len, chunk, chunks, splits, ws, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t stream)
+{
+    if (n < 0) return FMM_ERR_DIM;
+    if (n > 0 && (!x || !y)) return FMM_ERR_NULL;
+    FMM_HIP(f32_to_bf16(x, y, n, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_workspace_size(int32_t op, const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, int32_t dtype,
+                              size_t *bytes)
+{
+    if (!bytes) return FMM_ERR_NULL;
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    switch (op) {
+    case FMM_OP_SDDMM: *bytes = 0; return FMM_OK;
+    case FMM_OP_SPMM_A:
+    case FMM_OP_FUSEDMM_A: *bytes = partial_bytes(S_csr, r, k.obytes); return FMM_OK;
+    case FMM_OP_SPMM_B:
+    case FMM_OP_FUSEDMM_B: *bytes = partial_bytes(S_csc, r, k.obytes); return FMM_OK;
+    case FMM_OP_FUSEDMM_A_BWD:
+    case FMM_OP_FUSEDMM_B_BWD:
+    case FMM_OP_SDDMM_BWD:
+    case FMM_OP_SPMM_A_BWD:
+    case FMM_OP_SPMM_B_BWD: *bytes = max_partial(S_csr, S_csc, r, k.obytes); return FMM_OK;
+    default: return FMM_ERR_DIM;
+    }
+}
+
+// ---------------------------------------------------------------- forward
+
+fmm_status fmm_sddmm(const fmm_sparse *S, const void *A, const void *B, int32_t r, int32_t dtype, void *R, double beta,
+                     void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    (void)ws;
+    (void)ws_bytes;
+    FMM_TRY(check_sparse(S, -1));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    FMM_TRY(check_dense(A, S->rows, k.sbytes, r));
+    FMM_TRY(check_dense(B, S->cols, k.sbytes, r));
+    if (S->nnz > 0 && !R) return FMM_ERR_NULL;
+    LineArgs a = base_args(S, r, nullptr);
+    a.n_chunks = S->n_chunks;  // chunks only rebalance; SDDMM has no partials
+    const bool csr = S->orient == FMM_CSR;
+    a.H = csr ? A : B;
+    a.G1 = csr ? B : A;
+    a.out = R;
+    a.beta = beta;
+    fmm_sparse Sx = *S;
+    Sx.n_splits = 0;
+    FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'S', 'S', a, &Sx, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_spmm_a(const fmm_sparse *S_csr, const void *w, const void *B, int32_t r, int32_t dtype, void *C,
+                      double beta, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S_csr, FMM_CSR));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    FMM_TRY(check_dense(B, S_csr->cols, k.sbytes, r));
+    FMM_TRY(check_dense(C, S_csr->rows, k.obytes, r));
+    FMM_TRY(check_ws(S_csr, r, k.obytes, ws, ws_bytes));
+    LineArgs a = base_args(S_csr, r, ws);
+    if (w) { a.val = nullptr; a.wv1 = w; }
+    a.G1 = B;
+    a.out = C;
+    a.beta = beta;
+    FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csr, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_spmm_b(const fmm_sparse *S_csc, const void *w, int32_t w_order, const void *A, int32_t r, int32_t dtype,
+                      void *C, double beta, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S_csc, FMM_CSC));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    if (w && w_order != FMM_CSR && w_order != FMM_CSC) return FMM_ERR_ORIENT;
+    if (w && w_order == FMM_CSR && S_csc->nnz > 0 && !S_csc->perm) return FMM_ERR_NULL;
+    FMM_TRY(check_dense(A, S_csc->rows, k.sbytes, r));
+    FMM_TRY(check_dense(C, S_csc->cols, k.obytes, r));
+    FMM_TRY(check_ws(S_csc, r, k.obytes, ws, ws_bytes));
+    LineArgs a = base_args(S_csc, r, ws);
+    if (w) {
+        a.val = nullptr;
+        a.wv1 = w;
+        a.wperm = w_order == FMM_CSR ? S_csc->perm : nullptr;
+    }
+    a.G1 = A;
+    a.out = C;
+    a.beta = beta;
+    FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csc, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_fusedmm_a(const fmm_sparse *S_csr, const void *A, const void *B, int32_t r, int32_t dtype, void *C,
+                         int32_t flags, void *R_ws, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S_csr, FMM_CSR));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    FMM_TRY(check_dense(A, S_csr->rows, k.sbytes, r));
+    FMM_TRY(check_dense(B, S_csr->cols, k.sbytes, r));
+    FMM_TRY(check_dense(C, S_csr->rows, k.obytes, r));
+    FMM_TRY(check_ws(S_csr, r, k.obytes, ws, ws_bytes));
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (S_csr->nnz > 0 && !R_ws) return FMM_ERR_WORKSPACE;
+        LineArgs s = base_args(S_csr, r, nullptr);
+        s.H = A;
+        s.G1 = B;
+        s.out = R_ws;
+        fmm_sparse Sx = *S_csr;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'S', 'S', s, &Sx, stream));
+        LineArgs a = base_args(S_csr, r, ws);
+        a.val = nullptr;
+        a.wv1 = R_ws;
+        a.G1 = B;
+        a.out = C;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csr, stream));
+        return FMM_OK;
+    }
+    LineArgs a = base_args(S_csr, r, ws);
+    a.H = A;
+    a.G1 = B;
+    a.out = C;
+    FMM_HIP(run<OP_FUSED1>(k.path, 'S', 'S', 'S', a, S_csr, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_fusedmm_b(const fmm_sparse *S_csc, const void *A, const void *B, int32_t r, int32_t dtype, void *C,
+                         int32_t flags, void *R_ws, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S_csc, FMM_CSC));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    FMM_TRY(check_dense(A, S_csc->rows, k.sbytes, r));
+    FMM_TRY(check_dense(B, S_csc->cols, k.sbytes, r));
+    FMM_TRY(check_dense(C, S_csc->cols, k.obytes, r));
+    FMM_TRY(check_ws(S_csc, r, k.obytes, ws, ws_bytes));
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (S_csc->nnz > 0 && (!R_ws || !S_csc->perm)) return FMM_ERR_WORKSPACE;
+        // SDDMM on the transposed copy, written in CSR order (R keeps S's layout) ...
+        LineArgs s = base_args(S_csc, r, nullptr);
+        s.H = B;
+        s.G1 = A;
+        s.out = R_ws;
+        s.operm = S_csc->perm;
+        fmm_sparse Sx = *S_csc;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'S', 'S', s, &Sx, stream));
+        // ... then SpMMB reads it back through perm
+        LineArgs a = base_args(S_csc, r, ws);
+        a.val = nullptr;
+        a.wv1 = R_ws;
+        a.wperm = S_csc->perm;
+        a.G1 = A;
+        a.out = C;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csc, stream));
+        return FMM_OK;
+    }
+    LineArgs a = base_args(S_csc, r, ws);
+    a.H = B;
+    a.G1 = A;
+    a.out = C;
+    FMM_HIP(run<OP_FUSED1>(k.path, 'S', 'S', 'S', a, S_csc, stream));
+    return FMM_OK;
+}
+
+// ---------------------------------------------------------------- backward
+
+fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A, const void *B,
+                                  const void *dC, int32_t r, int32_t dtype, void *dA, void *dB, int32_t flags,
+                                  const void *R_ws, void *dP_ws, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    FMM_TRY(check_dense(dC, m, k.obytes, r));
+    if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
+    if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
+    FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (S_csr->nnz > 0 && (!dP_ws || (dB && (!R_ws || !S_csc->perm)))) return FMM_ERR_WORKSPACE;
+        LineArgs s = base_args(S_csr, r, nullptr);  // dP = S * (dC B^T)
+        s.H = dC;
+        s.G1 = B;
+        s.out = dP_ws;
+        fmm_sparse Sx = *S_csr;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'O', 'S', 'S', s, &Sx, stream));
+        if (dA) {  // dA = dP B
+            LineArgs a = base_args(S_csr, r, ws);
+            a.val = nullptr;
+            a.wv1 = dP_ws;
+            a.G1 = B;
+            a.out = dA;
+            FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csr, stream));
+        }
+        if (dB) {  // dB = dP^T A + R^T dC, both read through perm
+            LineArgs a = base_args(S_csc, r, ws);
+            a.val = nullptr;
+            a.wv1 = dP_ws;
+            a.wv2 = R_ws;
+            a.wperm = S_csc->perm;
+            a.G1 = A;
+            a.G2 = dC;
+            a.out = dB;
+            FMM_HIP(run<OP_SPMM2>(k.path, 'S', 'S', 'O', a, S_csc, stream));
+        }
+        return FMM_OK;
+    }
+    if (dA) {  // dA = FusedMMA(S, dC, B)
+        LineArgs a = base_args(S_csr, r, ws);
+        a.H = dC;
+        a.G1 = B;
+        a.out = dA;
+        FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S_csr, stream));
+    }
+    if (dB) {  // dB_j = sum_i S_ij (<B_j, dC_i> A_i + <B_j, A_i> dC_i)
+        LineArgs a = base_args(S_csc, r, ws);
+        a.H = B;
+        a.G1 = A;
+        a.G2 = dC;
+        a.out = dB;
+        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', 'O', a, S_csc, stream));
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A, const void *B,
+                                  const void *dC, int32_t r, int32_t dtype, void *dA, void *dB, int32_t flags,
+                                  const void *R_ws, void *dP_ws, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    FMM_TRY(check_dense(dC, n, k.obytes, r));
+    if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
+    if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
+    FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (S_csr->nnz > 0 && (!dP_ws || (dA && !R_ws) || (dB && !S_csc->perm))) return FMM_ERR_WORKSPACE;
+        LineArgs s = base_args(S_csr, r, nullptr);  // dP = S * (A dC^T), CSR order
+        s.H = A;
+        s.G1 = dC;
+        s.out = dP_ws;
+        fmm_sparse Sx = *S_csr;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'O', 'O', s, &Sx, stream));
+        if (dB) {  // dB = dP^T A through perm
+            LineArgs a = base_args(S_csc, r, ws);
+            a.val = nullptr;
+            a.wv1 = dP_ws;
+            a.wperm = S_csc->perm;
+            a.G1 = A;
+            a.out = dB;
+            FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csc, stream));
+        }
+        if (dA) {  // dA = dP B + R dC
+            LineArgs a = base_args(S_csr, r, ws);
+            a.val = nullptr;
+            a.wv1 = dP_ws;
+            a.wv2 = R_ws;
+            a.G1 = B;
+            a.G2 = dC;
+            a.out = dA;
+            FMM_HIP(run<OP_SPMM2>(k.path, 'S', 'S', 'O', a, S_csr, stream));
+        }
+        return FMM_OK;
+    }
+    if (dB) {  // dB = FusedMMB(S, A, dC): on the transposed copy, held dC_j, gathered A_i
+        LineArgs a = base_args(S_csc, r, ws);
+        a.H = dC;
+        a.G1 = A;
+        a.out = dB;
+        FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S_csc, stream));
+    }
+    if (dA) {  // dA_i = sum_j S_ij (<A_i, dC_j> B_j + <A_i, B_j> dC_j)
+        LineArgs a = base_args(S_csr, r, ws);
+        a.H = A;
+        a.G1 = B;
+        a.G2 = dC;
+        a.out = dA;
+        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', 'O', a, S_csr, stream));
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_sddmm_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A, const void *B,
+                              const void *dR, int32_t r, int32_t dtype, void *dA, void *dB, void *ws, size_t ws_bytes,
+                              hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
+    if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
+    if (S_csr->nnz > 0 && !dR) return FMM_ERR_NULL;
+    if (dB && S_csr->nnz > 0 && !S_csc->perm) return FMM_ERR_NULL;
+    FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
+    if (dA) {  // dA = (S * dR) B
+        LineArgs a = base_args(S_csr, r, ws);
+        a.wv1 = dR;
+        a.G1 = B;
+        a.out = dA;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csr, stream));
+    }
+    if (dB) {  // dB = (S * dR)^T A
+        LineArgs a = base_args(S_csc, r, ws);
+        a.wv1 = dR;
+        a.wperm = S_csc->perm;
+        a.G1 = A;
+        a.out = dB;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'S', 'S', 'S', a, S_csc, stream));
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_spmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *w, const void *B,
+                               const void *dC, int32_t r, int32_t dtype, void *dw, void *dB, void *ws, size_t ws_bytes,
+                               hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    FMM_TRY(check_dense(dC, m, k.obytes, r));
+    if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
+    if (w && dB && S_csr->nnz > 0 && !S_csc->perm) return FMM_ERR_NULL;
+    FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
+    if (dw && S_csr->nnz > 0) {  // dw[p] = <dC_i, B_j>
+        LineArgs s = base_args(S_csr, r, nullptr);
+        s.val = nullptr;
+        s.H = dC;
+        s.G1 = B;
+        s.out = dw;
+        fmm_sparse Sx = *S_csr;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'O', 'S', 'S', s, &Sx, stream));
+    }
+    if (dB) {  // dB = W^T dC
+        LineArgs a = base_args(S_csc, r, ws);
+        if (w) {
+            a.val = nullptr;
+            a.wv1 = w;
+            a.wperm = S_csc->perm;
+        }
+        a.G1 = dC;
+        a.out = dB;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'O', 'O', 'O', a, S_csc, stream));
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *w, const void *A,
+                               const void *dC, int32_t r, int32_t dtype, void *dw, void *dA, void *ws, size_t ws_bytes,
+                               hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(dC, n, k.obytes, r));
+    if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
+    FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
+    if (dw && S_csr->nnz > 0) {  // dw[p] = <A_i, dC_j>
+        LineArgs s = base_args(S_csr, r, nullptr);
+        s.val = nullptr;
+        s.H = A;
+        s.G1 = dC;
+        s.out = dw;
+        fmm_sparse Sx = *S_csr;
+        Sx.n_splits = 0;
+        FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'O', 'O', s, &Sx, stream));
+    }
+    if (dA) {  // dA = W dC
+        LineArgs a = base_args(S_csr, r, ws);
+        if (w) {
+            a.val = nullptr;
+            a.wv1 = w;
+        }
+        a.G1 = dC;
+        a.out = dA;
+        FMM_HIP(run<OP_SPMM1>(k.path, 'O', 'O', 'O', a, S_csr, stream));
+    }
+    return FMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,415 @@
+// Line kernels of the local FusedMM path for gfx950 (CDNA4, wave64).
+//
+// Every operation of the path walks the stored entries of S one major line at a
+// time (a row of the CSR, or a column of the stored transposed copy), touching for
+// each entry p = (line, idx[p]) one row of a "held" dense matrix H (the line's own
+// row, kept in registers) and one gathered row of G1 (and G2).  This is the shared
+// access pattern of SDDMM and SpMM the paper points out in Section IV-A.  The five
+// operations differ only in what they do per entry:
+//
+//   OP_SDDMM  : R[p]    = beta R[p] + w_p <H_line, G1_j>                  (Eq. (1))
+//   OP_SPMM1  : out_line = beta out + sum_p w_p G1_j                       (SpMMA/SpMMB)
+//   OP_SPMM2  : out_line = beta out + sum_p (w_p G1_j + w'_p G2_j)         (two SpMMs, one pass)
+//   OP_FUSED1 : out_line = beta out + sum_p w_p <H_line, G1_j> G1_j        (FusedMMA row form,
+//                                                                           Section IV-B)
+//   OP_FUSED2 : out_line = beta out + sum_p w_p (<H,G2_j> G1_j + <H,G1_j> G2_j)
+//               (the column pass of the adjoints: both sampled products recomputed)
+//
+// Work decomposition.  A group of L lanes (L | 64) owns one line; lane l holds
+// elements k = (v*L + l)*VW + e (v < NV, e < VW) of each r-vector, so one vector
+// load per (v, entry) covers a contiguous L*VW-element span: coalesced 16-byte
+// loads per lane.  A dot product is a lane-local FMA chain followed by an
+// all-reduce over the group with DPP row permutes (quad_perm, row_half_mirror,
+// row_mirror) and the gfx950 permlane16/32 swaps; every lane ends with the same
+// sum, so no broadcast is needed and no LDS is touched.  U entries are loaded
+// before any of them is reduced, to keep U row gathers in flight per group.
+//
+// Long lines: with a split schedule, lines longer than long_len are skipped by
+// the line groups and processed as chunks (line, begin, end) whose partial
+// r-vectors go to a workspace; merge_kernel adds them in chunk order.  Chunk
+// blocks come first in the grid so the heaviest items start first.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmm {
+
+typedef uint16_t bf16_t;
+
+enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4 };
+
+constexpr int kBlock = 256;
+
+struct LineArgs {
+    int32_t nlines;
+    int32_t r;
+    const int32_t *ptr;
+    const int32_t *idx;
+    const void *val;      // per-entry weight in orientation order (Acc), NULL = 1
+    const void *wv1;      // extra per-entry factor for G1 (Acc), NULL = 1
+    const void *wv2;      // extra per-entry factor for G2 (Acc), NULL = 1 (OP_SPMM2)
+    const int32_t *wperm; // wv1/wv2 are read at wperm[p] instead of p when non-NULL
+    const int32_t *operm; // OP_SDDMM writes R[operm[p]] instead of R[p] when non-NULL
+    const void *H;
+    const void *G1;
+    const void *G2;
+    void *out;            // lines x r (Acc), or nnz (Acc) for OP_SDDMM
+    double beta;
+    int32_t long_len;
+    int32_t n_chunks;
+    const int32_t *chunks;
+    void *partial;        // n_chunks x r (Acc)
+};
+
+// ------------------------------------------------------------------ conversions
+
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+
+// Load VW consecutive elements of T at p (16-byte vector loads where VW*sizeof(T)
+// is a multiple of 16) and widen them to Acc.
+template <class T, int VW, class Acc> struct Ld;
+
+template <> struct Ld<float, 1, float> {
+    static __device__ __forceinline__ void run(const float *p, float *o) { o[0] = p[0]; }
+};
+template <> struct Ld<float, 4, float> {
+    static __device__ __forceinline__ void run(const float *p, float *o) {
+        float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+};
+template <> struct Ld<float, 8, float> {
+    static __device__ __forceinline__ void run(const float *p, float *o) {
+        float4 v = reinterpret_cast<const float4 *>(p)[0];
+        float4 w = reinterpret_cast<const float4 *>(p)[1];
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+        o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+    }
+};
+template <> struct Ld<bf16_t, 8, float> {
+    static __device__ __forceinline__ void run(const bf16_t *p, float *o) {
+        uint4 v = *reinterpret_cast<const uint4 *>(p);
+        o[0] = bf16_lo(v.x); o[1] = bf16_hi(v.x); o[2] = bf16_lo(v.y); o[3] = bf16_hi(v.y);
+        o[4] = bf16_lo(v.z); o[5] = bf16_hi(v.z); o[6] = bf16_lo(v.w); o[7] = bf16_hi(v.w);
+    }
+};
+template <> struct Ld<double, 1, double> {
+    static __device__ __forceinline__ void run(const double *p, double *o) { o[0] = p[0]; }
+};
+template <> struct Ld<double, 2, double> {
+    static __device__ __forceinline__ void run(const double *p, double *o) {
+        double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x; o[1] = v.y;
+    }
+};
+
+template <class Acc, int VW> struct St;
+template <> struct St<float, 1> {
+    static __device__ __forceinline__ void run(float *p, const float *v) { p[0] = v[0]; }
+};
+template <> struct St<float, 4> {
+    static __device__ __forceinline__ void run(float *p, const float *v) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+template <> struct St<float, 8> {
+    static __device__ __forceinline__ void run(float *p, const float *v) {
+        reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+};
+template <> struct St<double, 1> {
+    static __device__ __forceinline__ void run(double *p, const double *v) { p[0] = v[0]; }
+};
+template <> struct St<double, 2> {
+    static __device__ __forceinline__ void run(double *p, const double *v) {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    }
+};
+
+// ------------------------------------------------------------------ group all-reduce
+
+template <int CTRL> __device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float swap16_sum(float x) {
+    auto s = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false, false);
+    return __int_as_float(s[0]) + __int_as_float(s[1]);
+}
+__device__ __forceinline__ float swap32_sum(float x) {
+    auto s = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
+    return __int_as_float(s[0]) + __int_as_float(s[1]);
+}
+
+// Sum over an aligned group of L lanes; every lane of the group gets the same value.
+// Each step adds the value of a partner lane in the other half of the current
+// span, and a + b == b + a exactly, so partners agree bit for bit.
+template <int L> __device__ __forceinline__ float group_sum(float x) {
+    if constexpr (L >= 2) x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+    if constexpr (L >= 4) x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+    if constexpr (L >= 8) x += dpp_f<0x141>(x);  // row_half_mirror
+    if constexpr (L >= 16) x += dpp_f<0x140>(x); // row_mirror
+    if constexpr (L >= 32) x = swap16_sum(x);
+    if constexpr (L >= 64) x = swap32_sum(x);
+    return x;
+}
+
+template <int CTRL> __device__ __forceinline__ double dpp_d(double x) {
+    int2 v = *reinterpret_cast<int2 *>(&x);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, 0xF, 0xF, false);
+    o.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, 0xF, 0xF, false);
+    return *reinterpret_cast<double *>(&o);
+}
+__device__ __forceinline__ double swap16_sum(double x) {
+    int2 v = *reinterpret_cast<int2 *>(&x);
+    auto a = __builtin_amdgcn_permlane16_swap(v.x, v.x, false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(v.y, v.y, false, false);
+    int2 p0 = make_int2(a[0], b[0]), p1 = make_int2(a[1], b[1]);
+    return *reinterpret_cast<double *>(&p0) + *reinterpret_cast<double *>(&p1);
+}
+__device__ __forceinline__ double swap32_sum(double x) {
+    int2 v = *reinterpret_cast<int2 *>(&x);
+    auto a = __builtin_amdgcn_permlane32_swap(v.x, v.x, false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(v.y, v.y, false, false);
+    int2 p0 = make_int2(a[0], b[0]), p1 = make_int2(a[1], b[1]);
+    return *reinterpret_cast<double *>(&p0) + *reinterpret_cast<double *>(&p1);
+}
+template <int L> __device__ __forceinline__ double group_sum(double x) {
+    if constexpr (L >= 2) x += dpp_d<0xB1>(x);
+    if constexpr (L >= 4) x += dpp_d<0x4E>(x);
+    if constexpr (L >= 8) x += dpp_d<0x141>(x);
+    if constexpr (L >= 16) x += dpp_d<0x140>(x);
+    if constexpr (L >= 32) x = swap16_sum(x);
+    if constexpr (L >= 64) x = swap32_sum(x);
+    return x;
+}
+
+// ------------------------------------------------------------------ the line kernel
+
+template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U>
+__global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chunk_blocks)
+{
+    constexpr int GPB = kBlock / L;  // groups per block
+    constexpr int E = NV * VW;       // elements per lane
+    const int lane = threadIdx.x % L;
+    const int gib = threadIdx.x / L;
+    const int r = a.r;
+
+    int32_t line, begin, end;
+    Acc *dst = nullptr;
+    bool to_partial = false;
+    if ((int32_t)blockIdx.x < nb_chunk_blocks) {
+        const int32_t c = blockIdx.x * GPB + gib;
+        if (c >= a.n_chunks) return;
+        line = a.chunks[3 * c];
+        begin = a.chunks[3 * c + 1];
+        end = a.chunks[3 * c + 2];
+        if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.partial) + (size_t)c * r;
+        to_partial = true;
+    } else {
+        line = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
+        if (line >= a.nlines) return;
+        begin = a.ptr[line];
+        end = a.ptr[line + 1];
+        if (a.n_chunks > 0 && end - begin > a.long_len) return;
+        if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.out) + (size_t)line * r;
+    }
+
+    // vector chunks this lane owns inside an r-vector
+    const int C = r / VW;
+    bool act[NV];
+    int off[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int cidx = v * L + lane;
+        act[v] = cidx < C;
+        off[v] = cidx * VW;
+    }
+
+    const int32_t *__restrict__ idx = a.idx;
+    const Acc *__restrict__ val = static_cast<const Acc *>(a.val);
+    const Acc *__restrict__ wv1 = static_cast<const Acc *>(a.wv1);
+    const Acc *__restrict__ wv2 = static_cast<const Acc *>(a.wv2);
+    const int32_t *__restrict__ wperm = a.wperm;
+    const TG1 *__restrict__ G1 = static_cast<const TG1 *>(a.G1);
+    const TG2 *__restrict__ G2 = static_cast<const TG2 *>(a.G2);
+
+    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
+    constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
+
+    Acc h[E];
+    if constexpr (kHeld) {
+        const TH *__restrict__ Hrow = static_cast<const TH *>(a.H) + (size_t)line * r;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (act[v]) {
+                Ld<TH, VW, Acc>::run(Hrow + off[v], h + v * VW);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) h[v * VW + e] = Acc(0);
+            }
+        }
+    }
+
+    Acc acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = Acc(0);
+
+    for (int32_t p0 = begin; p0 < end; p0 += U) {
+        int32_t j[U];
+        Acc w1[U], w2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = p0 + u;
+            const bool ok = p < end;
+            j[u] = ok ? idx[p] : -1;
+            Acc base = (ok && val) ? val[p] : Acc(ok ? 1 : 0);
+            if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
+                const int32_t q = (ok && wperm) ? wperm[p] : p;
+                w1[u] = (ok && wv1) ? base * wv1[q] : base;
+                if constexpr (OP == OP_SPMM2) w2[u] = (ok && wv2) ? base * wv2[q] : base;
+            } else {
+                w1[u] = base;
+            }
+        }
+        Acc g1[U][E];
+        Acc g2[kTwo ? U : 1][kTwo ? E : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = j[u] >= 0;
+            const TG1 *row1 = G1 + (size_t)(ok ? j[u] : 0) * r;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (ok && act[v]) {
+                    Ld<TG1, VW, Acc>::run(row1 + off[v], &g1[u][v * VW]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) g1[u][v * VW + e] = Acc(0);
+                }
+            }
+            if constexpr (kTwo) {
+                const TG2 *row2 = G2 + (size_t)(ok ? j[u] : 0) * r;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (ok && act[v]) {
+                        Ld<TG2, VW, Acc>::run(row2 + off[v], &g2[u][v * VW]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) g2[u][v * VW + e] = Acc(0);
+                    }
+                }
+            }
+        }
+
+        if constexpr (OP == OP_SPMM1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += w1[u] * g1[u][e];
+        } else if constexpr (OP == OP_SPMM2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += w1[u] * g1[u][e] + w2[u] * g2[u][e];
+        } else if constexpr (OP == OP_FUSED2) {
+            Acc d1[U], d2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Acc s1 = Acc(0), s2 = Acc(0);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    s1 += h[e] * g2[u][e];
+                    s2 += h[e] * g1[u][e];
+                }
+                d1[u] = s1;
+                d2[u] = s2;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                d1[u] = group_sum<L>(d1[u]);
+                d2[u] = group_sum<L>(d2[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const Acc c1 = w1[u] * d1[u], c2 = w1[u] * d2[u];
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += c1 * g1[u][e] + c2 * g2[u][e];
+            }
+        } else {
+            Acc d[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Acc s = Acc(0);
+#pragma unroll
+                for (int e = 0; e < E; ++e) s += h[e] * g1[u][e];
+                d[u] = s;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) d[u] = group_sum<L>(d[u]);
+            if constexpr (OP == OP_SDDMM) {
+                Acc *R = static_cast<Acc *>(a.out);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t p = p0 + u;
+                    if (lane == (u % L) && p < end) {
+                        const Acc res = w1[u] * d[u];
+                        const int64_t o = a.operm ? a.operm[p] : p;
+                        R[o] = (a.beta == 0.0) ? res : Acc(a.beta) * R[o] + res;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Acc c = w1[u] * d[u];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[e] += c * g1[u][e];
+                }
+            }
+        }
+    }
+
+    if constexpr (OP != OP_SDDMM) {
+        const bool keep = !to_partial && a.beta != 0.0;
+        const Acc beta = Acc(a.beta);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (act[v]) {
+                Acc o[VW];
+                if (keep) {
+                    Ld<Acc, VW, Acc>::run(dst + off[v], o);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) o[e] = beta * o[e] + acc[v * VW + e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) o[e] = acc[v * VW + e];
+                }
+                St<Acc, VW>::run(dst + off[v], o);
+            }
+        }
+    }
+}
+
+// Sum the chunk partials of every split line, in chunk order, into its output row:
+// out[line] = beta * out[line] + sum_c partial[first + c].
+template <class Acc>
+__global__ __launch_bounds__(kBlock) void merge_kernel(const int32_t *__restrict__ splits,
+                                                       int32_t n_splits, int32_t r,
+                                                       const Acc *__restrict__ partial,
+                                                       Acc *__restrict__ out, double beta)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n_splits * r) return;
+    const int32_t s = (int32_t)(t / r);
+    const int32_t k = (int32_t)(t % r);
+    const int32_t line = splits[3 * s], first = splits[3 * s + 1], cnt = splits[3 * s + 2];
+    Acc sum = Acc(0);
+    for (int32_t c = 0; c < cnt; ++c) sum += partial[(size_t)(first + c) * r + k];
+    Acc *o = out + (size_t)line * r + k;
+    *o = (beta == 0.0) ? sum : Acc(beta) * *o + sum;
+}
+
+}  // namespace fmm

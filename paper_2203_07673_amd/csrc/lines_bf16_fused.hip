@@ -1,0 +1,8 @@
+// Line-kernel instantiations for bfloat16 storage of A and B: the fused passes.
+#include "fmm_launch.hpp"
+
+namespace fmm {
+FMM_INSTANTIATE(OP_FUSED1, bf16_t, bf16_t, bf16_t, float)
+FMM_INSTANTIATE(OP_FUSED1, float, bf16_t, bf16_t, float)
+FMM_INSTANTIATE(OP_FUSED2, bf16_t, bf16_t, float, float)
+}  // namespace fmm

@@ -1,0 +1,451 @@
+"""Python binding of the local FusedMM library: sparse pattern objects and the
+autograd-enabled operations.
+
+PyTorch supplies device memory and the current stream; every arithmetic step runs
+in libfmm.so (see include/fmm.h).  Operations (Section II of the paper):
+
+  sddmm(P, A, B)      R = S * (A B^T) at S's stored entries, CSR order (Eq. (1))
+  spmm_a(P, B, w)     S B   (or W B with stored values w)
+  spmm_b(P, A, w)     S^T A (or W^T A)
+  fusedmm_a(P, A, B)  SpMMA(SDDMM(A, B, S), B)
+  fusedmm_b(P, A, B)  SpMMB(SDDMM(A, B, S), A), on the stored transposed copy
+
+A and B may be float32, bfloat16 (storage; float32 accumulation and outputs) or
+float64.  Gradients flow to A, B (and to w for the SpMMs); S's values are constants.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+__all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
+           "device_info", "dtype_code"]
+
+DEFAULT_LONG_LEN = 256
+DEFAULT_CHUNK = 256
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return C.FMM_F32
+    if t.dtype == torch.bfloat16:
+        return C.FMM_BF16
+    if t.dtype == torch.float64:
+        return C.FMM_F64
+    raise TypeError(f"unsupported dense dtype {t.dtype}")
+
+
+def _out_dtype(code: int):
+    return torch.float64 if code == C.FMM_F64 else torch.float32
+
+
+def _dev_tensor(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+def _check_dense(name, t, rows, r, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, pattern on {device}")
+    if t.dim() != 2 or t.shape[0] != rows or (r is not None and t.shape[1] != r):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({rows}, {r if r is not None else 'r'})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+
+
+class Pattern:
+    """A sparse matrix S (m x n) resident on the GPU in both orientations.
+
+    Holds the canonical CSR (rowptr, colidx, val), the stored transposed copy
+    (colptr, rowidx, valT, perm) built by the library's GPU transpose, and, where
+    some line has more than ``long_len`` entries, the split schedules of both
+    orientations.  The pattern is validated once at construction; later calls
+    trust it.
+    """
+
+    def __init__(self, rowptr, colidx, val, shape, *, device=None, val_dtype=torch.float32, validate=True,
+                 long_len: int = DEFAULT_LONG_LEN, chunk: int = DEFAULT_CHUNK, split: bool = True):
+        device = torch.device(device or "cuda")
+        if device.type != "cuda":
+            raise ValueError("Pattern lives on a GPU device")
+        C.load()
+        self.device = device
+        self.m, self.n = int(shape[0]), int(shape[1])
+        self.rowptr = _dev_tensor(rowptr, torch.int32, device)
+        self.colidx = _dev_tensor(colidx, torch.int32, device)
+        self.val = _dev_tensor(val, val_dtype, device) if val is not None else None
+        self.val_dtype = val_dtype
+        self.nnz = int(self.colidx.numel())
+        if self.rowptr.numel() != self.m + 1:
+            raise ValueError("rowptr must have m + 1 entries")
+        if self.val is not None and self.val.numel() != self.nnz:
+            raise ValueError("val must have nnz entries")
+        self._csr_sched = None
+        self._csc_sched = None
+        self._ws_cache = {}
+        if validate:
+            C.call("fmm_validate", ctypes.byref(self._desc(C.FMM_CSR, with_sched=False)), _stream())
+        self._transpose()
+        if split:
+            self._csr_sched = self._schedule(self.rowptr, self.m, long_len, chunk)
+            self._csc_sched = self._schedule(self.colptr, self.n, long_len, chunk)
+        self.csr = self._desc(C.FMM_CSR)
+        self.csc = self._desc(C.FMM_CSC)
+
+    @classmethod
+    def from_csr(cls, S, **kw):
+        """From any object with m, n, rowptr, colidx, val (e.g. workloads.CsrPattern)."""
+        vd = torch.float64 if np.asarray(S.val).dtype == np.float64 else torch.float32
+        kw.setdefault("val_dtype", vd)
+        return cls(S.rowptr, S.colidx, S.val, (S.m, S.n), **kw)
+
+    def _transpose(self):
+        bytes_ = ctypes.c_size_t(0)
+        C.call("fmm_csr_to_csc_workspace", self.m, self.n, self.nnz, ctypes.byref(bytes_))
+        ws = torch.empty(max(1, bytes_.value), dtype=torch.uint8, device=self.device)
+        self.colptr = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        self.rowidx = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        self.perm = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        self.valT = (torch.empty(self.nnz, dtype=self.val_dtype, device=self.device)
+                     if self.val is not None else None)
+        vcode = C.FMM_F64 if self.val_dtype == torch.float64 else C.FMM_F32
+        C.call("fmm_csr_to_csc", self.m, self.n, self.nnz, _ptr(self.rowptr), _ptr(self.colidx), _ptr(self.val),
+               vcode, _ptr(self.colptr), _ptr(self.rowidx), _ptr(self.valT), _ptr(self.perm), _ptr(ws),
+               bytes_.value, _stream())
+        torch.cuda.current_stream().synchronize()
+        del ws
+
+    def _schedule(self, ptr, nmajor, long_len, chunk):
+        bytes_ = ctypes.c_size_t(0)
+        C.call("fmm_schedule_workspace", nmajor, ctypes.byref(bytes_))
+        ws = torch.empty(max(1, bytes_.value), dtype=torch.uint8, device=self.device)
+        nch, nsp = ctypes.c_int32(0), ctypes.c_int32(0)
+        C.call("fmm_schedule_count", _ptr(ptr), nmajor, long_len, chunk, ctypes.byref(nch), ctypes.byref(nsp),
+               _ptr(ws), bytes_.value, _stream())
+        if nsp.value == 0:
+            return None
+        chunks = torch.empty(3 * nch.value, dtype=torch.int32, device=self.device)
+        splits = torch.empty(3 * nsp.value, dtype=torch.int32, device=self.device)
+        C.call("fmm_schedule_fill", _ptr(ptr), nmajor, long_len, chunk, _ptr(chunks), _ptr(splits), _ptr(ws),
+               bytes_.value, _stream())
+        torch.cuda.current_stream().synchronize()
+        return {"long_len": long_len, "chunk": chunk, "n_chunks": nch.value, "n_splits": nsp.value,
+                "chunks": chunks, "splits": splits}
+
+    def _desc(self, orient, with_sched=True):
+        d = C.fmm_sparse()
+        d.orient = orient
+        d.rows, d.cols, d.nnz = self.m, self.n, self.nnz
+        if orient == C.FMM_CSR:
+            d.ptr, d.idx, d.val = self.rowptr.data_ptr(), self.colidx.data_ptr(), _ptr(self.val)
+            sch = self._csr_sched
+        else:
+            d.ptr, d.idx, d.val = self.colptr.data_ptr(), self.rowidx.data_ptr(), _ptr(self.valT)
+            d.perm = self.perm.data_ptr()
+            sch = self._csc_sched
+        if with_sched and sch is not None:
+            d.long_len, d.n_chunks, d.n_splits = sch["long_len"], sch["n_chunks"], sch["n_splits"]
+            d.chunks, d.splits = sch["chunks"].data_ptr(), sch["splits"].data_ptr()
+        return d
+
+    def descriptor(self, orient, schedule=True):
+        """fmm_sparse descriptor for the C ABI (schedule=False drops the split schedule)."""
+        if schedule:
+            return self.csr if orient == C.FMM_CSR else self.csc
+        return self._desc(orient, with_sched=False)
+
+    @property
+    def schedules(self):
+        return {"csr": self._csr_sched, "csc": self._csc_sched}
+
+    def workspace(self, op: int, r: int, dcode: int):
+        """Device workspace for a call (cached by size); None when not needed."""
+        bytes_ = ctypes.c_size_t(0)
+        C.call("fmm_workspace_size", op, ctypes.byref(self.csr), ctypes.byref(self.csc), r, dcode,
+               ctypes.byref(bytes_))
+        if bytes_.value == 0:
+            return None, 0
+        ws = self._ws_cache.get(bytes_.value)
+        if ws is None:
+            ws = torch.empty(bytes_.value, dtype=torch.uint8, device=self.device)
+            self._ws_cache[bytes_.value] = ws
+        return ws, bytes_.value
+
+
+def _common(P: Pattern, A, B):
+    dcode = dtype_code(A)
+    if B is not None and B.dtype != A.dtype:
+        raise TypeError(f"A is {A.dtype} but B is {B.dtype}")
+    want = torch.float64 if dcode == C.FMM_F64 else torch.float32
+    if P.val is not None and P.val_dtype != want:
+        raise TypeError(f"pattern values are {P.val_dtype}; {A.dtype} storage needs {want}")
+    return dcode, _out_dtype(dcode)
+
+
+# ---------------------------------------------------------------- raw calls (no autograd)
+
+def fusedmm_a_raw(P, A, B, out=None, fused=True, R_ws=None):
+    r = A.shape[1]
+    _check_dense("A", A, P.m, r, P.device)
+    _check_dense("B", B, P.n, r, P.device)
+    dcode, odt = _common(P, A, B)
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    if not fused and R_ws is None:
+        R_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A, r, dcode)
+    C.call("fmm_fusedmm_a", ctypes.byref(P.csr), _ptr(A), _ptr(B), r, dcode, _ptr(out),
+           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(ws), wb, _stream())
+    return out, R_ws
+
+
+def fusedmm_b_raw(P, A, B, out=None, fused=True, R_ws=None):
+    r = A.shape[1]
+    _check_dense("A", A, P.m, r, P.device)
+    _check_dense("B", B, P.n, r, P.device)
+    dcode, odt = _common(P, A, B)
+    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else out
+    if not fused and R_ws is None:
+        R_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B, r, dcode)
+    C.call("fmm_fusedmm_b", ctypes.byref(P.csc), _ptr(A), _ptr(B), r, dcode, _ptr(out),
+           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(ws), wb, _stream())
+    return out, R_ws
+
+
+def fusedmm_a_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fused=True, R_ws=None, dP_ws=None):
+    r = A.shape[1]
+    dcode, odt = _common(P, A, B)
+    _check_dense("dC", dC, P.m, r, P.device)
+    if dC.dtype != odt:
+        raise TypeError(f"dC must be {odt}")
+    if need[0] and dA is None:
+        dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    if need[1] and dB is None:
+        dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    if not fused and dP_ws is None:
+        dP_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A_BWD, r, dcode)
+    C.call("fmm_fusedmm_a_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
+           dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
+           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
+    return dA, dB
+
+
+def fusedmm_b_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fused=True, R_ws=None, dP_ws=None):
+    r = A.shape[1]
+    dcode, odt = _common(P, A, B)
+    _check_dense("dC", dC, P.n, r, P.device)
+    if dC.dtype != odt:
+        raise TypeError(f"dC must be {odt}")
+    if need[0] and dA is None:
+        dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    if need[1] and dB is None:
+        dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    if not fused and dP_ws is None:
+        dP_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B_BWD, r, dcode)
+    C.call("fmm_fusedmm_b_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
+           dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
+           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
+    return dA, dB
+
+
+def sddmm_raw(P, A, B, out=None, orient=C.FMM_CSR, beta=0.0):
+    r = A.shape[1]
+    _check_dense("A", A, P.m, r, P.device)
+    _check_dense("B", B, P.n, r, P.device)
+    dcode, odt = _common(P, A, B)
+    out = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if out is None else out
+    desc = P.csr if orient == C.FMM_CSR else P.csc
+    C.call("fmm_sddmm", ctypes.byref(desc), _ptr(A), _ptr(B), r, dcode, _ptr(out), float(beta), None, 0, _stream())
+    return out[:P.nnz]
+
+
+def spmm_a_raw(P, B, w=None, out=None, beta=0.0):
+    r = B.shape[1]
+    _check_dense("B", B, P.n, r, P.device)
+    dcode, odt = _common(P, B, None)
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    ws, wb = P.workspace(C.FMM_OP_SPMM_A, r, dcode)
+    C.call("fmm_spmm_a", ctypes.byref(P.csr), _ptr(w), _ptr(B), r, dcode, _ptr(out), float(beta), _ptr(ws), wb,
+           _stream())
+    return out
+
+
+def spmm_b_raw(P, A, w=None, w_order=C.FMM_CSR, out=None, beta=0.0):
+    r = A.shape[1]
+    _check_dense("A", A, P.m, r, P.device)
+    dcode, odt = _common(P, A, None)
+    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else out
+    ws, wb = P.workspace(C.FMM_OP_SPMM_B, r, dcode)
+    C.call("fmm_spmm_b", ctypes.byref(P.csc), _ptr(w), w_order, _ptr(A), r, dcode, _ptr(out), float(beta),
+           _ptr(ws), wb, _stream())
+    return out
+
+
+# ---------------------------------------------------------------- autograd functions
+
+class _FusedMMA(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, A, B, fused):
+        C_out, R_ws = fusedmm_a_raw(P, A, B, fused=fused)
+        ctx.P, ctx.fused, ctx.R = P, fused, R_ws
+        ctx.save_for_backward(A, B)
+        return C_out
+
+    @staticmethod
+    def backward(ctx, dC):
+        A, B = ctx.saved_tensors
+        need = (ctx.needs_input_grad[1], ctx.needs_input_grad[2])
+        if not any(need):
+            return None, None, None, None
+        dA, dB = fusedmm_a_backward_raw(ctx.P, A, B, dC.contiguous(), need=need, fused=ctx.fused, R_ws=ctx.R)
+        return None, dA, dB, None
+
+
+class _FusedMMB(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, A, B, fused):
+        C_out, R_ws = fusedmm_b_raw(P, A, B, fused=fused)
+        ctx.P, ctx.fused, ctx.R = P, fused, R_ws
+        ctx.save_for_backward(A, B)
+        return C_out
+
+    @staticmethod
+    def backward(ctx, dC):
+        A, B = ctx.saved_tensors
+        need = (ctx.needs_input_grad[1], ctx.needs_input_grad[2])
+        if not any(need):
+            return None, None, None, None
+        dA, dB = fusedmm_b_backward_raw(ctx.P, A, B, dC.contiguous(), need=need, fused=ctx.fused, R_ws=ctx.R)
+        return None, dA, dB, None
+
+
+class _SDDMM(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, A, B):
+        ctx.P = P
+        ctx.save_for_backward(A, B)
+        return sddmm_raw(P, A, B)
+
+    @staticmethod
+    def backward(ctx, dR):
+        A, B = ctx.saved_tensors
+        P = ctx.P
+        r = A.shape[1]
+        dcode, odt = _common(P, A, B)
+        dR = dR.contiguous()
+        dA = torch.empty(P.m, r, dtype=odt, device=P.device) if ctx.needs_input_grad[1] else None
+        dB = torch.empty(P.n, r, dtype=odt, device=P.device) if ctx.needs_input_grad[2] else None
+        ws, wb = P.workspace(C.FMM_OP_SDDMM_BWD, r, dcode)
+        C.call("fmm_sddmm_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dR), r, dcode,
+               _ptr(dA), _ptr(dB), _ptr(ws), wb, _stream())
+        return None, dA, dB
+
+
+class _SpMMA(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, B, w):
+        ctx.P = P
+        ctx.save_for_backward(B, w)
+        return spmm_a_raw(P, B, w)
+
+    @staticmethod
+    def backward(ctx, dC):
+        B, w = ctx.saved_tensors
+        P = ctx.P
+        r = B.shape[1]
+        dcode, odt = _common(P, B, None)
+        dC = dC.contiguous()
+        dB = torch.empty(P.n, r, dtype=odt, device=P.device) if ctx.needs_input_grad[1] else None
+        dw = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if ctx.needs_input_grad[2] else None
+        ws, wb = P.workspace(C.FMM_OP_SPMM_A_BWD, r, dcode)
+        C.call("fmm_spmm_a_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(w), _ptr(B), _ptr(dC), r,
+               dcode, _ptr(dw), _ptr(dB), _ptr(ws), wb, _stream())
+        return None, dB, (dw[:P.nnz] if dw is not None else None)
+
+
+class _SpMMB(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, A, w):
+        ctx.P = P
+        ctx.save_for_backward(A, w)
+        return spmm_b_raw(P, A, w, C.FMM_CSR)
+
+    @staticmethod
+    def backward(ctx, dC):
+        A, w = ctx.saved_tensors
+        P = ctx.P
+        r = A.shape[1]
+        dcode, odt = _common(P, A, None)
+        dC = dC.contiguous()
+        dA = torch.empty(P.m, r, dtype=odt, device=P.device) if ctx.needs_input_grad[1] else None
+        dw = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if ctx.needs_input_grad[2] else None
+        ws, wb = P.workspace(C.FMM_OP_SPMM_B_BWD, r, dcode)
+        C.call("fmm_spmm_b_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(w), _ptr(A), _ptr(dC), r,
+               dcode, _ptr(dw), _ptr(dA), _ptr(ws), wb, _stream())
+        return None, dA, (dw[:P.nnz] if dw is not None else None)
+
+
+def fusedmm_a(P: Pattern, A, B, fused: bool = True):
+    """FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B), differentiable in A and B."""
+    return _FusedMMA.apply(P, A, B, fused)
+
+
+def fusedmm_b(P: Pattern, A, B, fused: bool = True):
+    """FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A), differentiable in A and B."""
+    return _FusedMMB.apply(P, A, B, fused)
+
+
+def sddmm(P: Pattern, A, B):
+    """Stored values of S * (A B^T) in CSR order (Eq. (1)), differentiable in A and B."""
+    return _SDDMM.apply(P, A, B)
+
+
+def spmm_a(P: Pattern, B, w=None):
+    """S B, or W B where W has S's pattern and stored values w (CSR order)."""
+    return _SpMMA.apply(P, B, w)
+
+
+def spmm_b(P: Pattern, A, w=None):
+    """S^T A, or W^T A where W has S's pattern and stored values w (CSR order)."""
+    return _SpMMB.apply(P, A, w)
+
+
+def to_bf16(x: torch.Tensor) -> torch.Tensor:
+    """Round a float32 device tensor to bfloat16 storage with the library's kernel
+    (nearest, ties to even)."""
+    if x.dtype != torch.float32 or not x.is_cuda:
+        raise TypeError("to_bf16 takes a float32 GPU tensor")
+    x = x.contiguous()
+    y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    C.call("fmm_f32_to_bf16", _ptr(x), _ptr(y), x.numel(), _stream())
+    return y
+
+
+def set_tuning(lanes: int = 0, nv: int = 0):
+    """Force the lane-group shape of later launches ((0, 0) = automatic)."""
+    C.call("fmm_set_tuning", lanes, nv)
+
+
+def device_info():
+    cu = ctypes.c_int32(0)
+    buf = ctypes.create_string_buffer(64)
+    C.call("fmm_device_info", ctypes.byref(cu), buf, 64)
+    return {"num_cu": cu.value, "arch": buf.value.decode()}

@@ -1,0 +1,128 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/fmm.h, and rejects invalid arguments with the documented status
+before touching the device (pointer values below are never dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2203_07673_amd as F
+from paper_2203_07673_amd import _capi as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fmm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = C.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in C.SIGNATURES, n
+    assert lib.fmm_abi_version() == 1
+
+
+def test_status_strings():
+    for code in range(0, -10, -1):
+        assert C.status_string(code) and C.status_string(code) != "unknown status"
+    assert C.status_string(5) == "unknown status"
+
+
+FAKE = 0x100000  # 16-byte aligned, never dereferenced
+
+
+def _desc(orient=C.FMM_CSR, rows=4, cols=5, nnz=6):
+    d = C.fmm_sparse()
+    d.orient, d.rows, d.cols, d.nnz = orient, rows, cols, nnz
+    d.ptr, d.idx, d.val = FAKE, FAKE, FAKE
+    return d
+
+
+def _fa(d, r=32, dtype=C.FMM_F32, A=FAKE, B=FAKE, Cp=FAKE, flags=0, R=None, ws=None, wsb=0):
+    return C.load().fmm_fusedmm_a(ctypes.byref(d) if d is not None else None, A, B, r, dtype, Cp, flags, R, ws, wsb,
+                                  None)
+
+
+def test_argument_errors_forward():
+    d = _desc()
+    assert _fa(None) == -1
+    assert _fa(_desc(orient=C.FMM_CSC)) == -4
+    assert _fa(_desc(orient=7)) == -4
+    assert _fa(_desc(rows=-1)) == -2
+    assert _fa(d, r=0) == -3
+    assert _fa(d, dtype=9) == -3
+    assert _fa(d, r=12, dtype=C.FMM_BF16) == -3          # bf16 needs r % 8 == 0
+    assert _fa(d, r=2048) == -3
+    assert _fa(d, r=301) == -3                           # r % 4 != 0 above 256
+    assert _fa(d, A=None) == -1
+    assert _fa(d, Cp=None) == -1
+    assert _fa(d, A=FAKE + 4) == -8                      # misaligned vector rows
+    assert _fa(d, flags=5) == -2
+    assert _fa(d, flags=C.FMM_UNFUSED, R=None) == -7     # unfused needs R workspace
+    d.ptr = None
+    assert _fa(d) == -1
+
+
+def test_workspace_rules_with_schedule():
+    d = _desc()
+    d.long_len, d.n_chunks, d.n_splits = 4, 10, 2
+    d.chunks, d.splits = FAKE, FAKE
+    lib = C.load()
+    nb = ctypes.c_size_t(0)
+    csc = _desc(orient=C.FMM_CSC)
+    assert lib.fmm_workspace_size(C.FMM_OP_FUSEDMM_A, ctypes.byref(d), ctypes.byref(csc), 32, C.FMM_F32,
+                                  ctypes.byref(nb)) == 0
+    assert nb.value == 10 * 32 * 4
+    assert lib.fmm_workspace_size(C.FMM_OP_FUSEDMM_A, ctypes.byref(d), ctypes.byref(csc), 32, C.FMM_F64,
+                                  ctypes.byref(nb)) == 0
+    assert nb.value == 10 * 32 * 8
+    assert lib.fmm_workspace_size(C.FMM_OP_SDDMM, ctypes.byref(d), None, 32, C.FMM_F32, ctypes.byref(nb)) == 0
+    assert nb.value == 0
+    assert _fa(d, ws=None) == -7
+    assert _fa(d, ws=FAKE, wsb=100) == -7
+    assert _fa(d, ws=FAKE + 8, wsb=1 << 20) == -7        # misaligned workspace
+    d.chunks = None
+    assert _fa(d, ws=FAKE, wsb=1 << 20) == -1
+
+
+def test_argument_errors_backward_and_prep():
+    lib = C.load()
+    csr, csc = _desc(), _desc(orient=C.FMM_CSC)
+    bad = _desc(orient=C.FMM_CSC, rows=3)
+    args = (FAKE, FAKE, FAKE, 32, C.FMM_F32, FAKE, FAKE, 0, None, None, None, 0, None)
+    assert lib.fmm_fusedmm_a_backward(ctypes.byref(csr), ctypes.byref(bad), *args) == -2
+    assert lib.fmm_fusedmm_a_backward(ctypes.byref(csc), ctypes.byref(csr), *args) == -4
+    assert lib.fmm_fusedmm_b_backward(None, ctypes.byref(csc), *args) == -1
+    uargs = (FAKE, FAKE, FAKE, 32, C.FMM_F32, FAKE, FAKE, C.FMM_UNFUSED, None, None, None, 0, None)
+    assert lib.fmm_fusedmm_a_backward(ctypes.byref(csr), ctypes.byref(csc), *uargs) == -7
+    nb = ctypes.c_size_t(0)
+    assert lib.fmm_csr_to_csc_workspace(10, 10, 100, ctypes.byref(nb)) == 0 and nb.value > 800
+    assert lib.fmm_csr_to_csc_workspace(-1, 10, 100, ctypes.byref(nb)) == -2
+    assert lib.fmm_csr_to_csc(10, 10, 100, FAKE, FAKE, None, 0, FAKE, FAKE, None, FAKE, None, 0, None) == -7
+    assert lib.fmm_csr_to_csc(10, 10, 100, None, FAKE, None, 0, FAKE, FAKE, None, FAKE, FAKE, 1 << 30, None) == -1
+    assert lib.fmm_csr_to_csc(10, 10, 100, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == -3
+    n1, n2 = ctypes.c_int32(0), ctypes.c_int32(0)
+    assert lib.fmm_schedule_count(FAKE, 10, 4, 8, ctypes.byref(n1), ctypes.byref(n2), FAKE, 1 << 20, None) == -2
+    assert lib.fmm_schedule_count(FAKE, 10, 8, 0, ctypes.byref(n1), ctypes.byref(n2), FAKE, 1 << 20, None) == -2
+    assert lib.fmm_schedule_count(FAKE, 10, 8, 8, ctypes.byref(n1), ctypes.byref(n2), None, 0, None) == -7
+    assert lib.fmm_f32_to_bf16(None, None, -1, None) == -2
+    assert lib.fmm_f32_to_bf16(None, FAKE, 4, None) == -1
+    assert lib.fmm_validate(None, None) == -1
+    assert lib.fmm_set_tuning(3, 1) == -8
+    assert lib.fmm_set_tuning(32, 0) == -2
+    assert lib.fmm_set_tuning(0, 0) == 0
+
+
+def test_python_layer_checks_before_calling():
+    import torch
+    with pytest.raises(TypeError):
+        F.dtype_code(torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        F.Pattern([0, 1], [0], [1.0], (1, 1), device="cpu")
