@@ -84,6 +84,8 @@ class Pattern:
         device = torch.device(device or "cuda")
         if device.type != "cuda":
             raise ValueError("Pattern lives on a GPU device")
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
         C.load()
         self.device = device
         self.m, self.n = int(shape[0]), int(shape[1])
