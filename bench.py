@@ -53,7 +53,7 @@ def kernel_bytes_min(kind, m, n, nnz, r, e):
     raise ValueError(kind)
 
 
-def cpu_baseline(w, target_s=12.0):
+def cpu_baseline(w, target_s=15.0):
     """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload."""
     from types import SimpleNamespace
 
@@ -74,14 +74,118 @@ def cpu_baseline(w, target_s=12.0):
         oracle.fusedmm_a_backward(Sk, A[:K], B, G[:K])
         return time.perf_counter() - t0, nz
 
-    K0 = min(S.m, 8192)
-    t0, _ = run(K0)
-    K = int(min(S.m, max(K0, K0 * target_s / max(t0, 1e-3))))
+    # grow the row sample until the timed run takes at least half the target time
+    K = min(S.m, 8192)
     t, nz = run(K)
+    while t < 0.5 * target_s and K < S.m:
+        K = int(min(S.m, max(2 * K, K * target_s / max(t, 1e-3))))
+        t, nz = run(K)
     gflops = 12.0 * r * nz / t / 1e9
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"first {K} of {S.m} rows ({nz} nonzeros), FusedMMA forward + adjoint in float64, "
                       f"{t:.1f} s"}
+
+COPY_BYTES = 1 << 30
+SRC_GLOBS = ("paper_2203_07673_amd/csrc/*.hip", "paper_2203_07673_amd/csrc/*.hpp")
+
+
+def source_hash():
+    """SHA-256 over the HIP sources: counter data is valid only for the kernels it measured."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for pat in SRC_GLOBS:
+        for f in sorted(glob.glob(os.path.join(ROOT, pat))):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _short_kernel(name):
+    if "line_kernel<" in name:
+        return "line_kernel<" + name.split("line_kernel<", 1)[1].split(">", 1)[0] + ">"
+    return name[:120]
+
+
+def pmc_summary(fetch_dir, write_dir, out_json, command=""):
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from two counter runs of the
+    same command, with scale factors from the plain device copy of COPY_BYTES bytes that
+    --calibrate-copy ran (found as the copy dispatches writing COPY_BYTES; the two runs
+    number their dispatches identically)."""
+    runs = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        runs[counter] = {}
+        for row in _csv_rows(d, "counter_collection.csv"):
+            if row.get("Counter_Name") == counter:
+                runs[counter][int(row["Dispatch_Id"])] = (row["Kernel_Name"], float(row["Counter_Value"]))
+    want_kib = COPY_BYTES / 1024.0
+    calib = [i for i, (k, v) in runs["WRITE_SIZE"].items()
+             if "copy" in k.lower() and abs(v - want_kib) < 0.01 * want_kib and i in runs["FETCH_SIZE"]]
+    scale = {"FETCH_SIZE": None, "WRITE_SIZE": None}
+    if calib:
+        for c in scale:
+            mean = sum(runs[c][i][1] for i in calib) / len(calib)
+            scale[c] = want_kib / mean if mean > 0 else None
+    kernels = {}
+    for c, per in runs.items():
+        for i, (k, v) in per.items():
+            if i in calib:
+                continue
+            kernels.setdefault(_short_kernel(k), {}).setdefault(c, []).append(v)
+    summary = {}
+    for k, v in kernels.items():
+        summary[k] = {c: sum(x) / len(x) for c, x in v.items()}
+        summary[k]["dispatches"] = max(len(x) for x in v.values())
+    out = {"command": command, "source_hash": source_hash(), "copy_bytes": COPY_BYTES,
+           "copy_dispatches": sorted(calib), "scale": scale,
+           "note": "KiB per dispatch as the counters read them; bytes = (FETCH*scale_f + WRITE*scale_w)*1024",
+           "kernels": summary}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def trace_summary(trace_dir, out_md, command=""):
+    rows = _csv_rows(trace_dir, "kernel_stats.csv")
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def load_traffic(workload_name, kernel_key):
+    """Counter-measured HBM bytes per launch of a kernel, if the committed counter summary
+    for this workload was taken on the current kernel sources (else None)."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t["kernels"].get(kernel_key)
+    sf, sw = t["scale"].get("FETCH_SIZE"), t["scale"].get("WRITE_SIZE")
+    if not k or sf is None or sw is None:
+        return None
+    return (k["FETCH_SIZE"] * sf + k["WRITE_SIZE"] * sw) * 1024.0
 
 
 def main():
@@ -92,7 +196,20 @@ def main():
     ap.add_argument("--workload", default="er1m_d32_r128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for counter scaling)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
+                    help="summarise a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, command=args.command)
+        return
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, command=args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
@@ -169,8 +286,19 @@ def main():
     dom_bytes = kernel_bytes(dom, m, n, nnz, r, e)
     achieved = dom_bytes / (kt[dom] * 1e-3) / 1e9
     step_bytes = sum(kernel_bytes(k, m, n, nnz, r, e) for k in kinds)
+    op_prefix = {"fwd": "line_kernel<3, float, float, float, float,",
+                 "bwd_row": "line_kernel<3, float, float, float, float,",
+                 "bwd_col": "line_kernel<4, float, float, float, float,"}[dom]
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            keys = [k for k in json.load(fh)["kernels"] if k.startswith(op_prefix)]
+        if len(keys) == 1:
+            traffic = load_traffic(args.workload, keys[0])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "kernel": {"fwd": "FusedMMA forward (line_kernel op 3)",
                            "bwd_row": "adjoint row pass dA (line_kernel op 3)",
                            "bwd_col": "adjoint column pass dB (line_kernel op 4)"}[dom],
@@ -215,6 +343,14 @@ def main():
         variants["pattern_prep_s"] = round(prep_s, 3)
         variants["step_bytes_gather_model"] = int(step_bytes)
         variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)
+
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,
