@@ -67,7 +67,9 @@ typedef enum fmm_status {
     FMM_ERR_NONCANONICAL = -6,  /* fmm_validate: duplicate or unsorted minor indices    */
     FMM_ERR_WORKSPACE = -7,     /* workspace missing or smaller than required           */
     FMM_ERR_UNSUPPORTED = -8,   /* valid request this build does not implement          */
-    FMM_ERR_HIP = -9            /* a HIP runtime call failed                           */
+    FMM_ERR_HIP = -9,           /* a HIP runtime call failed                           */
+    FMM_ERR_STATE = -10         /* batch plan not in the state the call needs (no graph
+                                   captured, or captured before the latest autotune)   */
 } fmm_status;
 
 typedef enum fmm_dtype { FMM_F32 = 0, FMM_BF16 = 1, FMM_F64 = 2 } fmm_dtype;
@@ -292,6 +294,83 @@ fmm_status fmm_spmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
 fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *w,
                                const void *A, const void *dC, int32_t r, int32_t dtype, void *dw,
                                void *dA, void *ws, size_t ws_bytes, hipStream_t stream);
+
+
+/* ---------------------------------------------------------------- batched graphs */
+
+/*
+ * Many independent graphs in one persistent launch (fused forward and/or adjoint of
+ * FusedMMA for every graph), optionally replayed from a captured hipGraph.  Each graph
+ * g has its own S_g (CSR, and CSC for the adjoint), A_g, B_g, upstream gradient dC_g
+ * and outputs; the operations are those of fmm_fusedmm_a / fmm_fusedmm_a_backward.
+ *
+ * The plan cuts every graph's lines into tiles of about tile_nnz stored entries,
+ * assigns tiles to a fixed grid of workgroups (one resident wave set per CU) and keeps
+ * the per-graph descriptor and tile tables in device memory it owns.  Schedules:
+ *   - row-block: L lanes per line, several lines per wave;
+ *   - wavefront-per-line: the 64 lanes of a wave share one line, each lane group
+ *     taking every (64/L)-th batch of entries, partial sums added across groups;
+ *   - XCD-aware placement: all tiles of a graph go to workgroups of one XCD (workgroup
+ *     ids are dealt round-robin over the 8 XCDs of gfx950), so a graph's gathered rows
+ *     stay in that XCD's L2.
+ * fmm_batch_autotune times candidate schedules with HIP events and keeps the fastest.
+ * Results are deterministic for a fixed schedule; with the row-block schedule they equal
+ * the single-graph calls bit for bit.
+ */
+#define FMM_BATCH_FWD 1   /* compute C_g = FusedMMA(S_g, A_g, B_g)                        */
+#define FMM_BATCH_BWD 2   /* compute dA_g, dB_g for upstream gradient dC_g                */
+
+typedef struct fmm_batch_graph {
+    fmm_sparse csr;       /* rows x cols CSR descriptor of S_g (its split schedule is ignored) */
+    fmm_sparse csc;       /* the stored transpose of S_g (required with FMM_BATCH_BWD)         */
+    const void *A;        /* rows x r, storage dtype                                           */
+    const void *B;        /* cols x r, storage dtype                                           */
+    const void *dC;       /* rows x r float32 upstream gradient (FMM_BATCH_BWD)                */
+    void *C;              /* rows x r float32 output (FMM_BATCH_FWD)                           */
+    void *dA;             /* rows x r float32 output (FMM_BATCH_BWD)                           */
+    void *dB;             /* cols x r float32 output (FMM_BATCH_BWD)                           */
+} fmm_batch_graph;
+
+typedef struct fmm_batch_plan fmm_batch_plan;
+
+typedef struct fmm_batch_info {
+    int32_t tile_nnz;       /* target stored entries per tile                              */
+    int32_t xcd_aware;      /* 1: graphs pinned to XCDs                                     */
+    int32_t lanes;          /* L                                                            */
+    int32_t row_schedule;   /* 0 row-block, 1 wavefront-per-line (forward and dA passes)    */
+    int32_t col_schedule;   /* same, for the dB column pass                                 */
+    int32_t n_tiles;
+    int32_t n_workgroups;
+    int32_t n_candidates;   /* schedules the last autotune timed (0 = never tuned)          */
+    float best_ms;          /* time of the chosen schedule in the last autotune             */
+    int32_t graph_captured; /* 1 when a hipGraph of the current schedule is instantiated    */
+} fmm_batch_info;
+
+/*
+ * Build a plan for nbatch graphs with common r and dtype (FMM_F32 or FMM_BF16 storage;
+ * r % (16 / element size) == 0 and r <= 64 * 16 / element size).  flags: FMM_BATCH_FWD
+ * and/or FMM_BATCH_BWD.  Synchronous: copies the pointer arrays of every graph to the
+ * host to cut nnz-balanced tiles, then allocates and uploads the tables.  The default
+ * schedule (before autotuning) is row-block, XCD-aware, tile_nnz 8192.  The graphs'
+ * device buffers must stay valid for the life of the plan.
+ */
+fmm_status fmm_batch_plan_create(const fmm_batch_graph *graphs, int32_t nbatch, int32_t r, int32_t dtype,
+                                 int32_t flags, fmm_batch_plan **plan);
+/* Time every candidate schedule (each run overwrites the outputs with the same values)
+   and keep the fastest.  Synchronous.  Invalidates a captured graph. */
+fmm_status fmm_batch_autotune(fmm_batch_plan *plan, hipStream_t stream);
+/* One persistent launch of the current schedule (eager). */
+fmm_status fmm_batch_run(fmm_batch_plan *plan, hipStream_t stream);
+/* Capture the current schedule's launch into a hipGraph and instantiate it.  stream must
+   be a created (non-null) stream; nothing else may be enqueued on it meanwhile. */
+fmm_status fmm_batch_capture(fmm_batch_plan *plan, hipStream_t stream);
+/* Replay the captured graph on stream (FMM_ERR_STATE if none is current). */
+fmm_status fmm_batch_launch(fmm_batch_plan *plan, hipStream_t stream);
+fmm_status fmm_batch_plan_info(const fmm_batch_plan *plan, fmm_batch_info *info);
+/* Force a schedule (as fmm_batch_autotune would pick it); invalidates a captured graph. */
+fmm_status fmm_batch_set_schedule(fmm_batch_plan *plan, int32_t tile_nnz, int32_t xcd_aware,
+                                  int32_t row_schedule, int32_t col_schedule);
+void fmm_batch_plan_destroy(fmm_batch_plan *plan);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@ include/fmm.h); this package is its Python binding.
 """
 from ._capi import FmmError, load as _load_library  # noqa: F401
 from .fusedmm import (  # noqa: F401
+    BatchPlan,
     Pattern,
     device_info,
     dtype_code,

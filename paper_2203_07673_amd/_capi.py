@@ -24,7 +24,8 @@ FMM_FUSED, FMM_UNFUSED = 0, 1
 
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_ERR_NULL", -2: "FMM_ERR_DIM", -3: "FMM_ERR_DTYPE", -4: "FMM_ERR_ORIENT",
                 -5: "FMM_ERR_INDEX", -6: "FMM_ERR_NONCANONICAL", -7: "FMM_ERR_WORKSPACE",
-                -8: "FMM_ERR_UNSUPPORTED", -9: "FMM_ERR_HIP"}
+                -8: "FMM_ERR_UNSUPPORTED", -9: "FMM_ERR_HIP", -10: "FMM_ERR_STATE"}
+FMM_BATCH_FWD, FMM_BATCH_BWD = 1, 2
 
 
 class fmm_sparse(ctypes.Structure):
@@ -43,6 +44,34 @@ class fmm_sparse(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("chunks", ctypes.c_void_p),
         ("splits", ctypes.c_void_p),
+    ]
+
+
+class fmm_batch_graph(ctypes.Structure):
+    _fields_ = [
+        ("csr", fmm_sparse),
+        ("csc", fmm_sparse),
+        ("A", ctypes.c_void_p),
+        ("B", ctypes.c_void_p),
+        ("dC", ctypes.c_void_p),
+        ("C", ctypes.c_void_p),
+        ("dA", ctypes.c_void_p),
+        ("dB", ctypes.c_void_p),
+    ]
+
+
+class fmm_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("tile_nnz", ctypes.c_int32),
+        ("xcd_aware", ctypes.c_int32),
+        ("lanes", ctypes.c_int32),
+        ("row_schedule", ctypes.c_int32),
+        ("col_schedule", ctypes.c_int32),
+        ("n_tiles", ctypes.c_int32),
+        ("n_workgroups", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32),
+        ("best_ms", ctypes.c_float),
+        ("graph_captured", ctypes.c_int32),
     ]
 
 
@@ -86,8 +115,16 @@ SIGNATURES = {
     "fmm_sddmm_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_a_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_b_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
+    "fmm_batch_plan_create": [ctypes.POINTER(fmm_batch_graph), _I32, _I32, _I32, _I32, ctypes.POINTER(_P)],
+    "fmm_batch_autotune": [_P, _P],
+    "fmm_batch_run": [_P, _P],
+    "fmm_batch_capture": [_P, _P],
+    "fmm_batch_launch": [_P, _P],
+    "fmm_batch_plan_info": [_P, ctypes.POINTER(fmm_batch_info)],
+    "fmm_batch_set_schedule": [_P, _I32, _I32, _I32, _I32],
+    "fmm_batch_plan_destroy": [_P],
 }
-_RESTYPE = {"fmm_status_string": ctypes.c_char_p}
+_RESTYPE = {"fmm_status_string": ctypes.c_char_p, "fmm_batch_plan_destroy": None}
 
 _lib = None
 

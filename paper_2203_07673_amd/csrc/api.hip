@@ -11,6 +11,7 @@
 namespace fmm {
 
 static thread_local int32_t g_last_hip_error = 0;
+void set_last_hip_error(int32_t e) { g_last_hip_error = e; }
 
 static Tuning g_tuning = {0, 0};
 Tuning &tuning() { return g_tuning; }
@@ -229,6 +230,7 @@ const char *fmm_status_string(int32_t status)
     case FMM_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case FMM_ERR_UNSUPPORTED: return "unsupported request (alignment or size limit)";
     case FMM_ERR_HIP: return "HIP runtime error";
+    case FMM_ERR_STATE: return "batch plan has no current captured graph";
     default: return "unknown status";
     }
 }

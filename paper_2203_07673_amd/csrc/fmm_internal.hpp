@@ -31,6 +31,9 @@ struct Tuning {
 };
 Tuning &tuning();
 
+// Record the hipError_t that fmm_last_hip_error() reports for this thread.
+void set_last_hip_error(int32_t e);
+
 // One launch of a line kernel (plus the merge of split lines for the accumulating ops).
 // Instantiated in lines_<dtype>.hip for the type combinations the C ABI uses.
 template <int OP, class TH, class TG1, class TG2, class Acc>

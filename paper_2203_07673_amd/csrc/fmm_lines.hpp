@@ -129,6 +129,56 @@ template <> struct St<double, 2> {
     }
 };
 
+// Raw vectors of a gathered row, kept in their storage type until each element is
+// used (bfloat16 stays packed: 4 registers per 8 elements instead of 8).
+template <class T, int VW> struct Raw;
+template <> struct Raw<float, 1> {
+    float x;
+    __device__ __forceinline__ void load(const float *p) { x = p[0]; }
+    __device__ __forceinline__ void zero() { x = 0.f; }
+    __device__ __forceinline__ float get(int) const { return x; }
+};
+template <> struct Raw<float, 4> {
+    float4 x;
+    __device__ __forceinline__ void load(const float *p) { x = *reinterpret_cast<const float4 *>(p); }
+    __device__ __forceinline__ void zero() { x = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ __forceinline__ float get(int e) const { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
+};
+template <> struct Raw<float, 8> {
+    float4 x, y;
+    __device__ __forceinline__ void load(const float *p) {
+        x = reinterpret_cast<const float4 *>(p)[0];
+        y = reinterpret_cast<const float4 *>(p)[1];
+    }
+    __device__ __forceinline__ void zero() { x = y = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ __forceinline__ float get(int e) const {
+        const float4 &q = e < 4 ? x : y;
+        const int f = e & 3;
+        return f == 0 ? q.x : f == 1 ? q.y : f == 2 ? q.z : q.w;
+    }
+};
+template <> struct Raw<bf16_t, 8> {
+    uint4 x;
+    __device__ __forceinline__ void load(const bf16_t *p) { x = *reinterpret_cast<const uint4 *>(p); }
+    __device__ __forceinline__ void zero() { x = make_uint4(0u, 0u, 0u, 0u); }
+    __device__ __forceinline__ float get(int e) const {
+        const uint32_t w = (e >> 1) == 0 ? x.x : (e >> 1) == 1 ? x.y : (e >> 1) == 2 ? x.z : x.w;
+        return (e & 1) ? bf16_hi(w) : bf16_lo(w);
+    }
+};
+template <> struct Raw<double, 1> {
+    double x;
+    __device__ __forceinline__ void load(const double *p) { x = p[0]; }
+    __device__ __forceinline__ void zero() { x = 0.0; }
+    __device__ __forceinline__ double get(int) const { return x; }
+};
+template <> struct Raw<double, 2> {
+    double2 x;
+    __device__ __forceinline__ void load(const double *p) { x = *reinterpret_cast<const double2 *>(p); }
+    __device__ __forceinline__ void zero() { x = make_double2(0.0, 0.0); }
+    __device__ __forceinline__ double get(int e) const { return e == 0 ? x.x : x.y; }
+};
+
 // ------------------------------------------------------------------ group all-reduce
 
 template <int CTRL> __device__ __forceinline__ float dpp_f(float x) {
@@ -188,13 +238,265 @@ template <int L> __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+// ------------------------------------------------------------------ cross-group sum
+
+// Sum over the GPL groups (of L lanes each) that share one wave when L * GPL == 64:
+// rotations inside 16-lane rows (row_ror by L, 2L, ...), then the row-pair and
+// half-wave swaps.  Every lane ends with a full sum; callers store group 0's copy.
+template <int L, int GPL> __device__ __forceinline__ float cross_group_sum(float x) {
+    static_assert(GPL == 1 || L * GPL == 64, "groups of a line must fill the wave");
+    if constexpr (GPL > 1) {
+        if constexpr (L < 16) {
+#pragma unroll
+            for (int s = L; s < 16; s <<= 1) {
+                if (s == 1) x += dpp_f<0x121>(x);
+                else if (s == 2) x += dpp_f<0x122>(x);
+                else if (s == 4) x += dpp_f<0x124>(x);
+                else x += dpp_f<0x128>(x);
+            }
+        }
+        if constexpr (L < 32) x = swap16_sum(x);
+        x = swap32_sum(x);
+    }
+    return x;
+}
+template <int L, int GPL> __device__ __forceinline__ double cross_group_sum(double x) {
+    static_assert(GPL == 1 || L * GPL == 64, "groups of a line must fill the wave");
+    if constexpr (GPL > 1) {
+        if constexpr (L < 16) {
+#pragma unroll
+            for (int s = L; s < 16; s <<= 1) {
+                if (s == 1) x += dpp_d<0x121>(x);
+                else if (s == 2) x += dpp_d<0x122>(x);
+                else if (s == 4) x += dpp_d<0x124>(x);
+                else x += dpp_d<0x128>(x);
+            }
+        }
+        if constexpr (L < 32) x = swap16_sum(x);
+        x = swap32_sum(x);
+    }
+    return x;
+}
+
+// ------------------------------------------------------------------ one line
+
+// Operands of a line pass (device pointers; types fixed by the template).
+struct LineOperands {
+    const int32_t *idx;
+    const void *val;
+    const void *wv1;
+    const void *wv2;
+    const int32_t *wperm;
+    const int32_t *operm;
+    const void *H;
+    const void *G1;
+    const void *G2;
+    void *R;  // OP_SDDMM output (nnz)
+    int32_t r;
+    double beta;
+};
+
+// Process entries [begin, end) of one major line.  GPL groups of L lanes may share the
+// line (GPL > 1: wavefront-per-line; group gidx takes every GPL-th batch of U entries
+// and the partial sums are added across groups at the end).  dst receives the line's
+// r-vector (beta applied when keep_beta); OP_SDDMM writes per-entry values instead.
+template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U, int GPL>
+__device__ __forceinline__ void process_line(const LineOperands &o, int lane, int gidx, int32_t line, int32_t begin,
+                                             int32_t end, Acc *dst, bool keep_beta)
+{
+    constexpr int E = NV * VW;  // elements per lane
+    const int r = o.r;
+
+    // vector chunks this lane owns inside an r-vector
+    const int C = r / VW;
+    bool act[NV];
+    int off[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int cidx = v * L + lane;
+        act[v] = cidx < C;
+        off[v] = cidx * VW;
+    }
+
+    const int32_t *__restrict__ idx = o.idx;
+    const Acc *__restrict__ val = static_cast<const Acc *>(o.val);
+    const Acc *__restrict__ wv1 = static_cast<const Acc *>(o.wv1);
+    const Acc *__restrict__ wv2 = static_cast<const Acc *>(o.wv2);
+    const int32_t *__restrict__ wperm = o.wperm;
+    const TG1 *__restrict__ G1 = static_cast<const TG1 *>(o.G1);
+    const TG2 *__restrict__ G2 = static_cast<const TG2 *>(o.G2);
+
+    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
+    constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
+
+    Acc h[E];
+    if constexpr (kHeld) {
+        const TH *__restrict__ Hrow = static_cast<const TH *>(o.H) + (size_t)line * r;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (act[v]) {
+                Ld<TH, VW, Acc>::run(Hrow + off[v], h + v * VW);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) h[v * VW + e] = Acc(0);
+            }
+        }
+    }
+
+    Acc acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = Acc(0);
+
+    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
+        int32_t j[U];
+        Acc w1[U], w2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = p0 + u;
+            const bool ok = p < end;
+            j[u] = ok ? idx[p] : -1;
+            Acc base = (ok && val) ? val[p] : Acc(ok ? 1 : 0);
+            if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
+                const int32_t q = (ok && wperm) ? wperm[p] : p;
+                w1[u] = (ok && wv1) ? base * wv1[q] : base;
+                if constexpr (OP == OP_SPMM2) w2[u] = (ok && wv2) ? base * wv2[q] : base;
+            } else {
+                w1[u] = base;
+            }
+        }
+        Raw<TG1, VW> g1[U][NV];
+        Raw<TG2, VW> g2[kTwo ? U : 1][kTwo ? NV : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = j[u] >= 0;
+            const TG1 *row1 = G1 + (size_t)(ok ? j[u] : 0) * r;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (ok && act[v]) g1[u][v].load(row1 + off[v]);
+                else g1[u][v].zero();
+            }
+            if constexpr (kTwo) {
+                const TG2 *row2 = G2 + (size_t)(ok ? j[u] : 0) * r;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (ok && act[v]) g2[u][v].load(row2 + off[v]);
+                    else g2[u][v].zero();
+                }
+            }
+        }
+
+        if constexpr (OP == OP_SPMM1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e));
+        } else if constexpr (OP == OP_SPMM2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e)) + w2[u] * Acc(g2[u][v].get(e));
+        } else if constexpr (OP == OP_FUSED2) {
+            Acc d1[U], d2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Acc s1 = Acc(0), s2 = Acc(0);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        s1 += h[v * VW + e] * Acc(g2[u][v].get(e));
+                        s2 += h[v * VW + e] * Acc(g1[u][v].get(e));
+                    }
+                d1[u] = s1;
+                d2[u] = s2;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                d1[u] = group_sum<L>(d1[u]);
+                d2[u] = group_sum<L>(d2[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const Acc c1 = w1[u] * d1[u], c2 = w1[u] * d2[u];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        acc[v * VW + e] += c1 * Acc(g1[u][v].get(e)) + c2 * Acc(g2[u][v].get(e));
+            }
+        } else {
+            Acc d[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Acc s = Acc(0);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) s += h[v * VW + e] * Acc(g1[u][v].get(e));
+                d[u] = s;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) d[u] = group_sum<L>(d[u]);
+            if constexpr (OP == OP_SDDMM) {
+                Acc *R = static_cast<Acc *>(o.R);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t p = p0 + u;
+                    if (lane == (u % L) && p < end) {
+                        const Acc res = w1[u] * d[u];
+                        const int64_t q = o.operm ? o.operm[p] : p;
+                        R[q] = (o.beta == 0.0) ? res : Acc(o.beta) * R[q] + res;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Acc c = w1[u] * d[u];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) acc[v * VW + e] += c * Acc(g1[u][v].get(e));
+                }
+            }
+        }
+    }
+
+    if constexpr (OP != OP_SDDMM) {
+        if constexpr (GPL > 1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = cross_group_sum<L, GPL>(acc[e]);
+            if (gidx != 0) return;
+        }
+        const Acc beta = Acc(o.beta);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (act[v]) {
+                Acc outv[VW];
+                if (keep_beta) {
+                    Ld<Acc, VW, Acc>::run(dst + off[v], outv);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) outv[e] = beta * outv[e] + acc[v * VW + e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) outv[e] = acc[v * VW + e];
+                }
+                St<Acc, VW>::run(dst + off[v], outv);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ the line kernel
 
 template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U>
 __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chunk_blocks)
 {
     constexpr int GPB = kBlock / L;  // groups per block
-    constexpr int E = NV * VW;       // elements per lane
     const int lane = threadIdx.x % L;
     const int gib = threadIdx.x / L;
     const int r = a.r;
@@ -218,179 +520,21 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
         if (a.n_chunks > 0 && end - begin > a.long_len) return;
         if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.out) + (size_t)line * r;
     }
-
-    // vector chunks this lane owns inside an r-vector
-    const int C = r / VW;
-    bool act[NV];
-    int off[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const int cidx = v * L + lane;
-        act[v] = cidx < C;
-        off[v] = cidx * VW;
-    }
-
-    const int32_t *__restrict__ idx = a.idx;
-    const Acc *__restrict__ val = static_cast<const Acc *>(a.val);
-    const Acc *__restrict__ wv1 = static_cast<const Acc *>(a.wv1);
-    const Acc *__restrict__ wv2 = static_cast<const Acc *>(a.wv2);
-    const int32_t *__restrict__ wperm = a.wperm;
-    const TG1 *__restrict__ G1 = static_cast<const TG1 *>(a.G1);
-    const TG2 *__restrict__ G2 = static_cast<const TG2 *>(a.G2);
-
-    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
-    constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
-
-    Acc h[E];
-    if constexpr (kHeld) {
-        const TH *__restrict__ Hrow = static_cast<const TH *>(a.H) + (size_t)line * r;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (act[v]) {
-                Ld<TH, VW, Acc>::run(Hrow + off[v], h + v * VW);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VW; ++e) h[v * VW + e] = Acc(0);
-            }
-        }
-    }
-
-    Acc acc[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = Acc(0);
-
-    for (int32_t p0 = begin; p0 < end; p0 += U) {
-        int32_t j[U];
-        Acc w1[U], w2[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t p = p0 + u;
-            const bool ok = p < end;
-            j[u] = ok ? idx[p] : -1;
-            Acc base = (ok && val) ? val[p] : Acc(ok ? 1 : 0);
-            if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
-                const int32_t q = (ok && wperm) ? wperm[p] : p;
-                w1[u] = (ok && wv1) ? base * wv1[q] : base;
-                if constexpr (OP == OP_SPMM2) w2[u] = (ok && wv2) ? base * wv2[q] : base;
-            } else {
-                w1[u] = base;
-            }
-        }
-        Acc g1[U][E];
-        Acc g2[kTwo ? U : 1][kTwo ? E : 1];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = j[u] >= 0;
-            const TG1 *row1 = G1 + (size_t)(ok ? j[u] : 0) * r;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                if (ok && act[v]) {
-                    Ld<TG1, VW, Acc>::run(row1 + off[v], &g1[u][v * VW]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) g1[u][v * VW + e] = Acc(0);
-                }
-            }
-            if constexpr (kTwo) {
-                const TG2 *row2 = G2 + (size_t)(ok ? j[u] : 0) * r;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (ok && act[v]) {
-                        Ld<TG2, VW, Acc>::run(row2 + off[v], &g2[u][v * VW]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VW; ++e) g2[u][v * VW + e] = Acc(0);
-                    }
-                }
-            }
-        }
-
-        if constexpr (OP == OP_SPMM1) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[e] += w1[u] * g1[u][e];
-        } else if constexpr (OP == OP_SPMM2) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[e] += w1[u] * g1[u][e] + w2[u] * g2[u][e];
-        } else if constexpr (OP == OP_FUSED2) {
-            Acc d1[U], d2[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                Acc s1 = Acc(0), s2 = Acc(0);
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    s1 += h[e] * g2[u][e];
-                    s2 += h[e] * g1[u][e];
-                }
-                d1[u] = s1;
-                d2[u] = s2;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                d1[u] = group_sum<L>(d1[u]);
-                d2[u] = group_sum<L>(d2[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const Acc c1 = w1[u] * d1[u], c2 = w1[u] * d2[u];
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[e] += c1 * g1[u][e] + c2 * g2[u][e];
-            }
-        } else {
-            Acc d[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                Acc s = Acc(0);
-#pragma unroll
-                for (int e = 0; e < E; ++e) s += h[e] * g1[u][e];
-                d[u] = s;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) d[u] = group_sum<L>(d[u]);
-            if constexpr (OP == OP_SDDMM) {
-                Acc *R = static_cast<Acc *>(a.out);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t p = p0 + u;
-                    if (lane == (u % L) && p < end) {
-                        const Acc res = w1[u] * d[u];
-                        const int64_t o = a.operm ? a.operm[p] : p;
-                        R[o] = (a.beta == 0.0) ? res : Acc(a.beta) * R[o] + res;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const Acc c = w1[u] * d[u];
-#pragma unroll
-                    for (int e = 0; e < E; ++e) acc[e] += c * g1[u][e];
-                }
-            }
-        }
-    }
-
-    if constexpr (OP != OP_SDDMM) {
-        const bool keep = !to_partial && a.beta != 0.0;
-        const Acc beta = Acc(a.beta);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (act[v]) {
-                Acc o[VW];
-                if (keep) {
-                    Ld<Acc, VW, Acc>::run(dst + off[v], o);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) o[e] = beta * o[e] + acc[v * VW + e];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) o[e] = acc[v * VW + e];
-                }
-                St<Acc, VW>::run(dst + off[v], o);
-            }
-        }
-    }
+    LineOperands o;
+    o.idx = a.idx;
+    o.val = a.val;
+    o.wv1 = a.wv1;
+    o.wv2 = a.wv2;
+    o.wperm = a.wperm;
+    o.operm = a.operm;
+    o.H = a.H;
+    o.G1 = a.G1;
+    o.G2 = a.G2;
+    o.R = a.out;
+    o.r = r;
+    o.beta = a.beta;
+    process_line<OP, TH, TG1, TG2, Acc, L, NV, VW, U, 1>(o, lane, 0, line, begin, end, dst,
+                                                         !to_partial && a.beta != 0.0);
 }
 
 // Sum the chunk partials of every split line, in chunk order, into its output row:

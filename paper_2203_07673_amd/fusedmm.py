@@ -24,7 +24,7 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code"]
+           "device_info", "dtype_code", "BatchPlan"]
 
 DEFAULT_LONG_LEN = 256
 DEFAULT_CHUNK = 256
@@ -451,3 +451,83 @@ def device_info():
     buf = ctypes.create_string_buffer(64)
     C.call("fmm_device_info", ctypes.byref(cu), buf, 64)
     return {"num_cu": cu.value, "arch": buf.value.decode()}
+
+
+class BatchPlan:
+    """Fused FusedMMA forward and/or adjoint over many graphs in one persistent launch.
+
+    ``patterns[g]``, ``A[g]`` (rows x r), ``B[g]`` (cols x r) and, for the adjoint,
+    ``dC[g]`` (rows x r float32) describe graph g.  Outputs ``C``, ``dA``, ``dB`` are
+    allocated here (lists of float32 tensors).  ``autotune()`` picks the schedule,
+    ``run()`` launches eagerly, ``capture(stream)`` records the launch in a hipGraph
+    and ``launch(stream)`` replays it.
+    """
+
+    def __init__(self, patterns, A, B, dC=None, forward=True, backward=True):
+        if not patterns:
+            raise ValueError("empty batch")
+        if backward and dC is None:
+            raise ValueError("the adjoint needs dC")
+        self.patterns, self.A, self.B, self.dC = list(patterns), list(A), list(B), dC
+        dev = patterns[0].device
+        r = A[0].shape[1]
+        dcode = dtype_code(A[0])
+        self.r, self.dcode = r, dcode
+        flags = (C.FMM_BATCH_FWD if forward else 0) | (C.FMM_BATCH_BWD if backward else 0)
+        self.C = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if forward else None
+        self.dA = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
+        self.dB = [torch.empty(P.n, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
+        arr = (C.fmm_batch_graph * len(patterns))()
+        for g, P in enumerate(patterns):
+            _check_dense("A", A[g], P.m, r, dev)
+            _check_dense("B", B[g], P.n, r, dev)
+            if A[g].dtype != A[0].dtype or B[g].dtype != A[0].dtype:
+                raise TypeError("all graphs need the same storage dtype")
+            x = arr[g]
+            x.csr = P.descriptor(C.FMM_CSR, schedule=False)
+            x.csc = P.descriptor(C.FMM_CSC, schedule=False)
+            x.A, x.B = A[g].data_ptr(), B[g].data_ptr()
+            if backward:
+                _check_dense("dC", dC[g], P.m, r, dev)
+                x.dC, x.dA, x.dB = dC[g].data_ptr(), self.dA[g].data_ptr(), self.dB[g].data_ptr()
+            if forward:
+                x.C = self.C[g].data_ptr()
+        self._arr = arr
+        self._plan = ctypes.c_void_p()
+        C.call("fmm_batch_plan_create", arr, len(patterns), r, dcode, flags, ctypes.byref(self._plan))
+
+    def autotune(self, stream=None):
+        C.call("fmm_batch_autotune", self._plan, self._s(stream))
+        return self.info()
+
+    def set_schedule(self, tile_nnz=8192, xcd_aware=True, row_wave=False, col_wave=False):
+        C.call("fmm_batch_set_schedule", self._plan, tile_nnz, int(xcd_aware), int(row_wave), int(col_wave))
+
+    def run(self, stream=None):
+        C.call("fmm_batch_run", self._plan, self._s(stream))
+
+    def capture(self, stream):
+        C.call("fmm_batch_capture", self._plan, self._s(stream))
+
+    def launch(self, stream):
+        C.call("fmm_batch_launch", self._plan, self._s(stream))
+
+    def info(self):
+        i = C.fmm_batch_info()
+        C.call("fmm_batch_plan_info", self._plan, ctypes.byref(i))
+        return {f: getattr(i, f) for f, _ in C.fmm_batch_info._fields_}
+
+    @staticmethod
+    def _s(stream):
+        if stream is None:
+            return _stream()
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan:
+            try:
+                C.load().fmm_batch_plan_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_status_strings():
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         assert C.status_string(code) and C.status_string(code) != "unknown status"
     assert C.status_string(5) == "unknown status"
 
@@ -126,3 +126,36 @@ def test_python_layer_checks_before_calling():
         F.dtype_code(torch.zeros(2, dtype=torch.int32))
     with pytest.raises(ValueError):
         F.Pattern([0, 1], [0], [1.0], (1, 1), device="cpu")
+
+
+def test_batch_plan_argument_errors():
+    lib = C.load()
+    plan = ctypes.c_void_p()
+    arr = (C.fmm_batch_graph * 2)()
+    for x in arr:
+        x.csr = _desc()
+        x.csc = _desc(orient=C.FMM_CSC)
+        x.A = x.B = x.dC = x.C = x.dA = x.dB = FAKE
+    create = lib.fmm_batch_plan_create
+    assert create(None, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -1
+    assert create(arr, 0, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -2
+    assert create(arr, 2, 64, C.FMM_F32, 0, ctypes.byref(plan)) == -2
+    assert create(arr, 2, 64, C.FMM_F64, 3, ctypes.byref(plan)) == -3
+    assert create(arr, 2, 12, C.FMM_BF16, 3, ctypes.byref(plan)) == -3
+    assert create(arr, 2, 2048, C.FMM_F32, 3, ctypes.byref(plan)) == -3
+    arr[1].csc = _desc(orient=C.FMM_CSR)
+    assert create(arr, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -4
+    arr[1].csc = _desc(orient=C.FMM_CSC, rows=9)
+    assert create(arr, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -2
+    arr[1].csc = _desc(orient=C.FMM_CSC)
+    arr[1].A = FAKE + 4
+    assert create(arr, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -8
+    arr[1].A = FAKE
+    arr[0].dB = None
+    assert create(arr, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -1
+    info = C.fmm_batch_info()
+    assert lib.fmm_batch_plan_info(None, ctypes.byref(info)) == -1
+    assert lib.fmm_batch_run(None, None) == -1
+    assert lib.fmm_batch_launch(None, None) == -1
+    assert lib.fmm_batch_autotune(None, None) == -1
+    assert lib.fmm_batch_set_schedule(None, 1, 0, 0, 0) == -1

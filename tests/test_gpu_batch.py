@@ -1,0 +1,127 @@
+"""Batched persistent launch over many uneven graphs: equality with the single-graph
+calls (bit for bit under the row-block schedule), oracle parity for every schedule,
+autotuning, and hipGraph replay against the eager launch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_07673_amd as F
+from tests.gates import TOL_BF16, TOL_F32
+from tests.gpu_helpers import gate, host, log, ref_fusedmm_a, ref_fusedmm_a_backward
+from workloads import batch_er
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(dtype, nbatch=12, r=64, seed=77):
+    graphs = batch_er(nbatch, r, seed=seed, nmin=64, nmax=4096, dmin=8, dmax=64)
+    pats = [F.Pattern.from_csr(g["S"]) for g in graphs]
+    A32 = [torch.from_numpy(g["A"]).cuda() for g in graphs]
+    B32 = [torch.from_numpy(g["B"]).cuda() for g in graphs]
+    G = [torch.from_numpy(g["G"]).cuda() for g in graphs]
+    if dtype == torch.bfloat16:
+        A = [F.to_bf16(a) for a in A32]
+        B = [F.to_bf16(b) for b in B32]
+    else:
+        A, B = A32, B32
+    return graphs, pats, A, B, G
+
+
+def _single(pats, A, B, G):
+    out = []
+    for P, a, b, g in zip(pats, A, B, G):
+        c, _ = F.fusedmm_a_raw(P, a, b)
+        da, db = F.fusedmm_a_backward_raw(P, a, b, g)
+        out.append((c, da, db))
+    torch.cuda.synchronize()
+    return out
+
+
+def _check_oracle(graphs, plan, tol, tag):
+    for k, g in enumerate(graphs):
+        S, A, B, G = g["S"], g["A"], g["B"], g["G"]
+        ref, mag = ref_fusedmm_a(S, A, B)
+        gate(f"{tag} graph {k} C", host(plan.C[k]), ref, mag, tol)
+        dA, dB, mA, mB = ref_fusedmm_a_backward(S, A, B, G)
+        gate(f"{tag} graph {k} dA", host(plan.dA[k]), dA, mA, tol)
+        gate(f"{tag} graph {k} dB", host(plan.dB[k]), dB, mB, tol)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_batch_row_block_equals_single_graph_calls(dtype):
+    graphs, pats, A, B, G = _setup(dtype)
+    log(f"batch row-block dtype={dtype} graphs={len(graphs)}")
+    plan = F.BatchPlan(pats, A, B, G)
+    for xcd in (True, False):
+        plan.set_schedule(tile_nnz=2048, xcd_aware=xcd, row_wave=False, col_wave=False)
+        plan.run()
+        torch.cuda.synchronize()
+        single = _single(pats, A, B, G)
+        for k, (c, da, db) in enumerate(single):
+            assert torch.equal(plan.C[k], c), (k, xcd)
+            assert torch.equal(plan.dA[k], da), (k, xcd)
+            assert torch.equal(plan.dB[k], db), (k, xcd)
+    _check_oracle(graphs, plan, TOL_BF16 if dtype == torch.bfloat16 else TOL_F32, "row-block")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_batch_wave_schedules_and_autotune(dtype):
+    graphs, pats, A, B, G = _setup(dtype, seed=78)
+    tol = TOL_BF16 if dtype == torch.bfloat16 else TOL_F32
+    plan = F.BatchPlan(pats, A, B, G)
+    for rw, cw in ((True, False), (False, True), (True, True)):
+        log(f"batch wave rw={rw} cw={cw} dtype={dtype}")
+        plan.set_schedule(tile_nnz=8192, xcd_aware=True, row_wave=rw, col_wave=cw)
+        plan.run()
+        torch.cuda.synchronize()
+        _check_oracle(graphs, plan, tol, f"wave rw={rw} cw={cw}")
+        first = [t.clone() for t in plan.C + plan.dA + plan.dB]
+        plan.run()
+        torch.cuda.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(first, plan.C + plan.dA + plan.dB))  # repeatable
+    log("batch autotune")
+    info = plan.autotune()
+    assert info["n_candidates"] >= 12 and info["best_ms"] > 0
+    plan.run()
+    torch.cuda.synchronize()
+    _check_oracle(graphs, plan, tol, "autotuned")
+
+
+def test_batch_graph_replay_matches_eager():
+    graphs, pats, A, B, G = _setup(torch.bfloat16, seed=79)
+    plan = F.BatchPlan(pats, A, B, G)
+    log("batch autotune + capture")
+    plan.autotune()
+    plan.run()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in plan.C + plan.dA + plan.dB]
+    side = torch.cuda.Stream()
+    with pytest.raises(F.FmmError):
+        plan.launch(side)  # nothing captured yet
+    plan.capture(side)
+    assert plan.info()["graph_captured"] == 1
+    for rep in range(3):
+        for t in plan.C + plan.dA + plan.dB:
+            t.zero_()  # eager work between replays
+        torch.cuda.synchronize()
+        plan.launch(side)
+        side.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(eager, plan.C + plan.dA + plan.dB)), rep
+    plan.set_schedule(tile_nnz=2048)  # a new schedule makes the captured graph stale
+    assert plan.info()["graph_captured"] == 0
+    with pytest.raises(F.FmmError):
+        plan.launch(side)
+
+
+def test_batch_forward_only_and_oracle_bf16_rounded():
+    graphs, pats, A, B, G = _setup(torch.bfloat16, nbatch=5, seed=80)
+    plan = F.BatchPlan(pats, A, B, forward=True, backward=False)
+    log("batch forward only")
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.dA is None
+    for k, g in enumerate(graphs):
+        Ar, Br = oracle.bf16_round(g["A"]), oracle.bf16_round(g["B"])
+        ref, mag = ref_fusedmm_a(g["S"], Ar, Br)
+        gate(f"fwd-only graph {k}", host(plan.C[k]), ref, mag, TOL_F32)
