@@ -30,9 +30,9 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(src, build_dir=None, defines=()):
+    obj = os.path.join(build_dir or BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the packed-fp32 feature and says so; drop that line
     err = "\n".join(l for l in p.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -43,21 +43,25 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None, verbose=True):
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs=None, verbose=True, out=None, build_dir=None, defines=()):
+    """Compile every csrc/*.hip and link libfmm.so (or `out`); `defines` are extra -D
+    macros (compile-time tuning constants of the kernels)."""
+    build_dir = build_dir or BUILD
+    lib = out or LIB
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(8, os.cpu_count() or 1, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + f".tmp{os.getpid()}"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), srcs))
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

@@ -9,9 +9,15 @@ namespace fmm {
 
 // Entries loaded ahead per group: enough gathers in flight without spilling.  A lane
 // holds U * NV vectors of 16 bytes per gathered matrix.
+#ifndef FMM_UNROLL_ONE
+#define FMM_UNROLL_ONE 8
+#endif
+#ifndef FMM_UNROLL_TWO
+#define FMM_UNROLL_TWO 4
+#endif
 template <int OP, int NV> constexpr int unroll_for() {
     constexpr bool two = (OP == OP_SPMM2 || OP == OP_FUSED2);
-    constexpr int u = (two ? 4 : 8) / NV;
+    constexpr int u = (two ? FMM_UNROLL_TWO : FMM_UNROLL_ONE) / NV;
     return u < 1 ? 1 : u;
 }
 

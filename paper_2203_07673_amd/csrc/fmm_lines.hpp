@@ -33,6 +33,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef FMM_PREFETCH_INDICES
+#define FMM_PREFETCH_INDICES 0
+#endif
+#ifndef FMM_NT_GATHER
+#define FMM_NT_GATHER 0
+#endif
+
 namespace fmm {
 
 typedef uint16_t bf16_t;
@@ -140,7 +147,15 @@ template <> struct Raw<float, 1> {
 };
 template <> struct Raw<float, 4> {
     float4 x;
-    __device__ __forceinline__ void load(const float *p) { x = *reinterpret_cast<const float4 *>(p); }
+    __device__ __forceinline__ void load(const float *p) {
+#if FMM_NT_GATHER
+        typedef float nf4 __attribute__((ext_vector_type(4)));
+        const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(p));
+        x = make_float4(v.x, v.y, v.z, v.w);
+#else
+        x = *reinterpret_cast<const float4 *>(p);
+#endif
+    }
     __device__ __forceinline__ void zero() { x = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
 };
@@ -159,7 +174,15 @@ template <> struct Raw<float, 8> {
 };
 template <> struct Raw<bf16_t, 8> {
     uint4 x;
-    __device__ __forceinline__ void load(const bf16_t *p) { x = *reinterpret_cast<const uint4 *>(p); }
+    __device__ __forceinline__ void load(const bf16_t *p) {
+#if FMM_NT_GATHER
+        typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
+        const nu4 v = __builtin_nontemporal_load(reinterpret_cast<const nu4 *>(p));
+        x = make_uint4(v.x, v.y, v.z, v.w);
+#else
+        x = *reinterpret_cast<const uint4 *>(p);
+#endif
+    }
     __device__ __forceinline__ void zero() { x = make_uint4(0u, 0u, 0u, 0u); }
     __device__ __forceinline__ float get(int e) const {
         const uint32_t w = (e >> 1) == 0 ? x.x : (e >> 1) == 1 ? x.y : (e >> 1) == 2 ? x.z : x.w;
@@ -328,6 +351,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 
     constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
     constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
+    constexpr bool kPrefetch = FMM_PREFETCH_INDICES != 0;
 
     Acc h[E];
     if constexpr (kHeld) {
@@ -347,9 +371,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = Acc(0);
 
-    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
-        int32_t j[U];
-        Acc w1[U], w2[U];
+    // indices and weights of the U entries starting at p0 (entries past `end` get j = -1)
+    auto load_batch = [&](int32_t p0, int32_t (&j)[U], Acc (&w1)[U], Acc (&w2)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
@@ -360,10 +383,19 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 const int32_t q = (ok && wperm) ? wperm[p] : p;
                 w1[u] = (ok && wv1) ? base * wv1[q] : base;
                 if constexpr (OP == OP_SPMM2) w2[u] = (ok && wv2) ? base * wv2[q] : base;
+                else w2[u] = Acc(0);
             } else {
                 w1[u] = base;
+                w2[u] = Acc(0);
             }
         }
+    };
+
+    int32_t j[U];
+    Acc w1[U], w2[U];
+    if (kPrefetch) load_batch(begin + gidx * U, j, w1, w2);
+    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
+        if (!kPrefetch) load_batch(p0, j, w1, w2);
         Raw<TG1, VW> g1[U][NV];
         Raw<TG2, VW> g2[kTwo ? U : 1][kTwo ? NV : 1];
 #pragma unroll
@@ -384,6 +416,12 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 }
             }
         }
+
+        // with prefetching, the next batch's indices are requested while this batch's
+        // rows are still in flight
+        int32_t jn[U];
+        Acc w1n[U], w2n[U];
+        if (kPrefetch) load_batch(p0 + U * GPL, jn, w1n, w2n);
 
         if constexpr (OP == OP_SPMM1) {
 #pragma unroll
@@ -462,6 +500,14 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
                         for (int e = 0; e < VW; ++e) acc[v * VW + e] += c * Acc(g1[u][v].get(e));
                 }
+            }
+        }
+        if (kPrefetch) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                j[u] = jn[u];
+                w1[u] = w1n[u];
+                w2[u] = w2n[u];
             }
         }
     }
