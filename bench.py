@@ -376,6 +376,8 @@ def main():
         return t, ktimes
 
     flops = 12.0 * r * nnz
+    tuned = P.autotune(A, B, G, form="a")
+    log(f"autotuned batch variants (f32): {tuned}")
     step_f32 = make_step(A, B, fused=True)
     log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
     t_step, kt = time_steps(step_f32, args.steps, args.warmup)
@@ -419,9 +421,11 @@ def main():
         log(f"unfused f32 step {t_unf * 1e3:.3f} ms")
         del R_ws, dP_ws
         A16, B16 = F.to_bf16(A), F.to_bf16(B)
+        tuned16 = P.autotune(A16, B16, G, form="a")
         t_bf, kt_bf = time_steps(make_step(A16, B16, fused=True), vsteps, 2)
         variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
-                                  "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()}}
+                                  "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()},
+                                  "batch_variants": tuned16}
         log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
         variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
         variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
@@ -467,6 +471,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "r": r, "storage": "f32",
+                   "batch_variants": tuned,
                    "step": "fused FusedMMA forward + adjoint (dA row pass, dB column pass)",
                    "flops_per_step": flops},
         "roofline": roofline,

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 1
+#define FMM_ABI_VERSION 2
 
 typedef enum fmm_status {
     FMM_OK = 0,
@@ -90,7 +90,17 @@ typedef enum fmm_orient { FMM_CSR = 0, FMM_CSC = 1 } fmm_orient;
  * Optional split schedule (from fmm_schedule_count / fmm_schedule_fill): major lines
  * with more than long_len stored entries are cut into chunks that run in parallel and
  * are summed afterwards in chunk order.  n_chunks == 0 disables it.
+ *
+ * variant: how many stored entries a lane group keeps in flight per batch (FMM_VARIANT_*).
+ * Deep batches suit long, uniform lines; shallow ones use fewer registers, so more lines
+ * are in flight at once, which suits many short lines.  FMM_VARIANT_AUTO picks from the
+ * mean line length (>= 24: deep, >= 6: medium, else shallow); fmm_autotune picks by
+ * timing.  Results differ only in summation order (all within the gate).
  */
+#define FMM_VARIANT_AUTO 0
+#define FMM_VARIANT_DEEP 1     /* 8 entries per batch (4 for the two-row passes) */
+#define FMM_VARIANT_MEDIUM 2   /* 4 (2)                                          */
+#define FMM_VARIANT_SHALLOW 3  /* 2 (1)                                          */
 typedef struct fmm_sparse {
     int32_t orient;
     int32_t rows, cols;
@@ -102,7 +112,7 @@ typedef struct fmm_sparse {
     int32_t long_len;          /* lines with more entries than this are split            */
     int32_t n_chunks;          /* number of chunk items                                  */
     int32_t n_splits;          /* number of split lines                                  */
-    int32_t reserved;
+    int32_t variant;           /* FMM_VARIANT_*                                            */
     const int32_t *chunks;     /* [3*n_chunks]: line, begin position, end position       */
     const int32_t *splits;     /* [3*n_splits]: line, first chunk, chunk count           */
 } fmm_sparse;
@@ -239,6 +249,19 @@ fmm_status fmm_fusedmm_a(const fmm_sparse *S_csr, const void *A, const void *B, 
 fmm_status fmm_fusedmm_b(const fmm_sparse *S_csc, const void *A, const void *B, int32_t r,
                          int32_t dtype, void *C, int32_t flags, void *R_ws, void *ws,
                          size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Choose the batch variant of S_csr and S_csc for the FusedMMA (op = FMM_OP_FUSEDMM_A_BWD)
+ * or FusedMMB (op = FMM_OP_FUSEDMM_B_BWD) forward and adjoint, by timing each variant on
+ * these operands with HIP events; writes S_csr->variant and S_csc->variant.  The pass that
+ * decides each orientation is the one that runs on it: the forward (and its same-shaped
+ * adjoint pass) for the operation's own orientation, the two-row adjoint pass for the
+ * other.  C (forward output), dA and dB are overwritten; ws as for the adjoint call.
+ * Synchronous.
+ */
+fmm_status fmm_autotune(int32_t op, fmm_sparse *S_csr, fmm_sparse *S_csc, const void *A, const void *B,
+                        const void *dC, int32_t r, int32_t dtype, void *C, void *dA, void *dB, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------- backward */
 

@@ -19,6 +19,7 @@ FMM_OK = 0
 FMM_F32, FMM_BF16, FMM_F64 = 0, 1, 2
 FMM_CSR, FMM_CSC = 0, 1
 FMM_FUSED, FMM_UNFUSED = 0, 1
+FMM_VARIANT_AUTO, FMM_VARIANT_DEEP, FMM_VARIANT_MEDIUM, FMM_VARIANT_SHALLOW = 0, 1, 2, 3
 (FMM_OP_SDDMM, FMM_OP_SPMM_A, FMM_OP_SPMM_B, FMM_OP_FUSEDMM_A, FMM_OP_FUSEDMM_B, FMM_OP_FUSEDMM_A_BWD,
  FMM_OP_FUSEDMM_B_BWD, FMM_OP_SDDMM_BWD, FMM_OP_SPMM_A_BWD, FMM_OP_SPMM_B_BWD) = range(10)
 
@@ -41,7 +42,7 @@ class fmm_sparse(ctypes.Structure):
         ("long_len", ctypes.c_int32),
         ("n_chunks", ctypes.c_int32),
         ("n_splits", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
         ("chunks", ctypes.c_void_p),
         ("splits", ctypes.c_void_p),
     ]
@@ -115,6 +116,7 @@ SIGNATURES = {
     "fmm_sddmm_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_a_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_b_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
+    "fmm_autotune": [_I32, _SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
     "fmm_batch_plan_create": [ctypes.POINTER(fmm_batch_graph), _I32, _I32, _I32, _I32, ctypes.POINTER(_P)],
     "fmm_batch_autotune": [_P, _P],
     "fmm_batch_run": [_P, _P],

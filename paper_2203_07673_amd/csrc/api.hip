@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <functional>
+
 #include "fmm.h"
 #include "fmm_internal.hpp"
 
@@ -98,6 +100,7 @@ fmm_status check_sparse(const fmm_sparse *S, int orient)
     if (!S->ptr) return FMM_ERR_NULL;
     if (S->nnz > 0 && !S->idx) return FMM_ERR_NULL;
     if (S->n_chunks < 0 || S->n_splits < 0) return FMM_ERR_DIM;
+    if (S->variant < FMM_VARIANT_AUTO || S->variant > FMM_VARIANT_SHALLOW) return FMM_ERR_DIM;
     if (S->n_chunks > 0) {
         if (!S->chunks || !S->splits) return FMM_ERR_NULL;
         if (S->long_len < 1 || S->n_splits < 1) return FMM_ERR_DIM;
@@ -122,10 +125,20 @@ fmm_status check_ws(const fmm_sparse *S, int32_t r, size_t obytes, void *ws, siz
     return FMM_OK;
 }
 
+// Batch depth class of a descriptor: its explicit variant, else by mean line length.
+int32_t unroll_class(const fmm_sparse *S)
+{
+    if (S->variant >= FMM_VARIANT_DEEP && S->variant <= FMM_VARIANT_SHALLOW) return S->variant;
+    const int64_t lines = S->orient == FMM_CSR ? S->rows : S->cols;
+    const double mean = lines > 0 ? (double)S->nnz / (double)lines : 0.0;
+    return mean >= 24.0 ? FMM_VARIANT_DEEP : mean >= 6.0 ? FMM_VARIANT_MEDIUM : FMM_VARIANT_SHALLOW;
+}
+
 LineArgs base_args(const fmm_sparse *S, int32_t r, void *ws)
 {
     LineArgs a;
     memset(&a, 0, sizeof(a));
+    a.uclass = unroll_class(S);
     a.nlines = nmajor(S);
     a.r = r;
     a.ptr = S->ptr;
@@ -740,6 +753,68 @@ fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
         FMM_HIP(run<OP_SPMM1>(k.path, 'O', 'O', 'O', a, S_csr, stream));
     }
     return FMM_OK;
+}
+
+// ---------------------------------------------------------------- variant autotuning
+
+fmm_status fmm_autotune(int32_t op, fmm_sparse *S_csr, fmm_sparse *S_csc, const void *A, const void *B, const void *dC,
+                        int32_t r, int32_t dtype, void *C, void *dA, void *dB, void *ws, size_t ws_bytes,
+                        hipStream_t stream)
+{
+    if (op != FMM_OP_FUSEDMM_A_BWD && op != FMM_OP_FUSEDMM_B_BWD) return FMM_ERR_DIM;
+    FMM_TRY(check_pair(S_csr, S_csc));
+    if (!C || !dA || !dB) return FMM_ERR_NULL;
+    const bool form_a = op == FMM_OP_FUSEDMM_A_BWD;
+    // the forward and its same-shaped adjoint pass run on `own`; the two-row pass on `other`
+    fmm_sparse *own = form_a ? S_csr : S_csc;
+    fmm_sparse *other = form_a ? S_csc : S_csr;
+    hipEvent_t e0, e1;
+    FMM_HIP(hipEventCreate(&e0));
+    FMM_HIP(hipEventCreate(&e1));
+    auto fwd = [&]() -> fmm_status {
+        return form_a ? fmm_fusedmm_a(S_csr, A, B, r, dtype, C, FMM_FUSED, nullptr, ws, ws_bytes, stream)
+                      : fmm_fusedmm_b(S_csc, A, B, r, dtype, C, FMM_FUSED, nullptr, ws, ws_bytes, stream);
+    };
+    auto two_row = [&]() -> fmm_status {
+        return form_a ? fmm_fusedmm_a_backward(S_csr, S_csc, A, B, dC, r, dtype, nullptr, dB, FMM_FUSED, nullptr,
+                                               nullptr, ws, ws_bytes, stream)
+                      : fmm_fusedmm_b_backward(S_csr, S_csc, A, B, dC, r, dtype, dA, nullptr, FMM_FUSED, nullptr,
+                                               nullptr, ws, ws_bytes, stream);
+    };
+    auto time_it = [&](const std::function<fmm_status()> &f, float *ms) -> fmm_status {
+        FMM_TRY(f());  // warm-up
+        FMM_HIP(hipEventRecord(e0, stream));
+        for (int i = 0; i < 3; ++i) FMM_TRY(f());
+        FMM_HIP(hipEventRecord(e1, stream));
+        FMM_HIP(hipEventSynchronize(e1));
+        FMM_HIP(hipEventElapsedTime(ms, e0, e1));
+        return FMM_OK;
+    };
+    fmm_status st = FMM_OK;
+    const int32_t keep_own = own->variant, keep_other = other->variant;
+    float best_own = 1e30f, best_other = 1e30f;
+    int32_t pick_own = keep_own, pick_other = keep_other;
+    for (int32_t v = FMM_VARIANT_DEEP; v <= FMM_VARIANT_SHALLOW && st == FMM_OK; ++v) {
+        float ms = 0.f;
+        own->variant = v;
+        st = time_it(fwd, &ms);
+        if (st == FMM_OK && ms < best_own) {
+            best_own = ms;
+            pick_own = v;
+        }
+        if (st != FMM_OK) break;
+        other->variant = v;
+        st = time_it(two_row, &ms);
+        if (st == FMM_OK && ms < best_other) {
+            best_other = ms;
+            pick_other = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    own->variant = st == FMM_OK ? pick_own : keep_own;
+    other->variant = st == FMM_OK ? pick_other : keep_other;
+    return st;
 }
 
 }  // extern "C"

@@ -9,23 +9,19 @@ namespace fmm {
 
 // Entries loaded ahead per group: enough gathers in flight without spilling.  A lane
 // holds U * NV vectors of 16 bytes per gathered matrix.
-#ifndef FMM_UNROLL_ONE
-#define FMM_UNROLL_ONE 8
-#endif
-#ifndef FMM_UNROLL_TWO
-#define FMM_UNROLL_TWO 4
-#endif
-template <int OP, int NV> constexpr int unroll_for() {
+// Batch depth of class CLS (1 deep, 2 medium, 3 shallow): entries per batch for the
+// one-row passes, half that for the two-row passes, divided by the vectors per lane.
+template <int OP, int NV, int CLS> constexpr int unroll_for() {
     constexpr bool two = (OP == OP_SPMM2 || OP == OP_FUSED2);
-    constexpr int u = (two ? FMM_UNROLL_TWO : FMM_UNROLL_ONE) / NV;
+    constexpr int one = CLS == 1 ? 8 : CLS == 2 ? 4 : 2;
+    constexpr int u = (two ? one / 2 : one) / NV;
     return u < 1 ? 1 : u;
 }
 
-template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW>
+template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U>
 hipError_t launch_one(const LineArgs &a, hipStream_t stream)
 {
     constexpr int GPB = kBlock / L;
-    constexpr int U = unroll_for<OP, NV>();
     const int64_t nb_chunk = a.n_chunks > 0 ? ((int64_t)a.n_chunks + GPB - 1) / GPB : 0;
     const int64_t nb_line = ((int64_t)a.nlines + GPB - 1) / GPB;
     const int64_t nb = nb_chunk + nb_line;
@@ -37,8 +33,11 @@ hipError_t launch_one(const LineArgs &a, hipStream_t stream)
 }
 
 #define FMM_SHAPE_CASE(Lv, NVv)                                                                  \
-    if (shape.L == Lv && shape.NV == NVv)                                                        \
-        return launch_one<OP, TH, TG1, TG2, Acc, Lv, NVv, VW>(a, stream);
+    if (shape.L == Lv && shape.NV == NVv) {                                                      \
+        if (a.uclass == 1) return launch_one<OP, TH, TG1, TG2, Acc, Lv, NVv, VW, unroll_for<OP, NVv, 1>()>(a, stream); \
+        if (a.uclass == 2) return launch_one<OP, TH, TG1, TG2, Acc, Lv, NVv, VW, unroll_for<OP, NVv, 2>()>(a, stream); \
+        return launch_one<OP, TH, TG1, TG2, Acc, Lv, NVv, VW, unroll_for<OP, NVv, 3>()>(a, stream);                    \
+    }
 
 template <int OP, class TH, class TG1, class TG2, class Acc, int VW>
 hipError_t launch_shape(const LineArgs &a, Shape shape, hipStream_t stream)

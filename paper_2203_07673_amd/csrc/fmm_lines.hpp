@@ -33,16 +33,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#ifndef FMM_PREFETCH_INDICES
-#define FMM_PREFETCH_INDICES 0
-#endif
-#ifndef FMM_NT_GATHER
-#define FMM_NT_GATHER 0
-#endif
 
 namespace fmm {
 
 typedef uint16_t bf16_t;
+
+// Stand-ins for absent per-entry arrays: read with stride 0 they give 1 (weights) or 0.
+static __device__ const float kUnitF[1] = {1.0f};
+static __device__ const double kUnitD[1] = {1.0};
+static __device__ const int32_t kZeroIdx[1] = {0};
+template <class Acc> __device__ __forceinline__ const Acc *unit_value();
+template <> __device__ __forceinline__ const float *unit_value<float>() { return kUnitF; }
+template <> __device__ __forceinline__ const double *unit_value<double>() { return kUnitD; }
+__device__ __forceinline__ const int32_t *zero_index() { return kZeroIdx; }
 
 enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4 };
 
@@ -67,6 +70,7 @@ struct LineArgs {
     int32_t n_chunks;
     const int32_t *chunks;
     void *partial;        // n_chunks x r (Acc)
+    int32_t uclass;       // batch depth class, 1 (deep) .. 3 (shallow)
 };
 
 // ------------------------------------------------------------------ conversions
@@ -141,26 +145,23 @@ template <> struct St<double, 2> {
 template <class T, int VW> struct Raw;
 template <> struct Raw<float, 1> {
     float x;
+    __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) { x = p[0]; }
     __device__ __forceinline__ void zero() { x = 0.f; }
     __device__ __forceinline__ float get(int) const { return x; }
 };
 template <> struct Raw<float, 4> {
     float4 x;
+    __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) {
-#if FMM_NT_GATHER
-        typedef float nf4 __attribute__((ext_vector_type(4)));
-        const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(p));
-        x = make_float4(v.x, v.y, v.z, v.w);
-#else
         x = *reinterpret_cast<const float4 *>(p);
-#endif
     }
     __device__ __forceinline__ void zero() { x = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
 };
 template <> struct Raw<float, 8> {
     float4 x, y;
+    __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) {
         x = reinterpret_cast<const float4 *>(p)[0];
         y = reinterpret_cast<const float4 *>(p)[1];
@@ -175,15 +176,12 @@ template <> struct Raw<float, 8> {
 template <> struct Raw<bf16_t, 8> {
     uint4 x;
     __device__ __forceinline__ void load(const bf16_t *p) {
-#if FMM_NT_GATHER
-        typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
-        const nu4 v = __builtin_nontemporal_load(reinterpret_cast<const nu4 *>(p));
-        x = make_uint4(v.x, v.y, v.z, v.w);
-#else
         x = *reinterpret_cast<const uint4 *>(p);
-#endif
     }
     __device__ __forceinline__ void zero() { x = make_uint4(0u, 0u, 0u, 0u); }
+    // Make the packed words opaque to the optimiser, so elements widened for the dot
+    // product are widened again for the update instead of staying live in between.
+    __device__ __forceinline__ void pin() { asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w)); }
     __device__ __forceinline__ float get(int e) const {
         const uint32_t w = (e >> 1) == 0 ? x.x : (e >> 1) == 1 ? x.y : (e >> 1) == 2 ? x.z : x.w;
         return (e & 1) ? bf16_hi(w) : bf16_lo(w);
@@ -191,12 +189,14 @@ template <> struct Raw<bf16_t, 8> {
 };
 template <> struct Raw<double, 1> {
     double x;
+    __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const double *p) { x = p[0]; }
     __device__ __forceinline__ void zero() { x = 0.0; }
     __device__ __forceinline__ double get(int) const { return x; }
 };
 template <> struct Raw<double, 2> {
     double2 x;
+    __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const double *p) { x = *reinterpret_cast<const double2 *>(p); }
     __device__ __forceinline__ void zero() { x = make_double2(0.0, 0.0); }
     __device__ __forceinline__ double get(int e) const { return e == 0 ? x.x : x.y; }
@@ -351,7 +351,6 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 
     constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
     constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
-    constexpr bool kPrefetch = FMM_PREFETCH_INDICES != 0;
 
     Acc h[E];
     if constexpr (kHeld) {
@@ -371,73 +370,85 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = Acc(0);
 
-    // indices and weights of the U entries starting at p0 (entries past `end` get j = -1)
-    auto load_batch = [&](int32_t p0, int32_t (&j)[U], Acc (&w1)[U], Acc (&w2)[U]) {
+    // Branch-free operand access: a NULL weight array is read as a single 1 (stride 0)
+    // and a NULL permutation as a single 0 plus the identity, so a full batch issues all
+    // of its loads back to back, with no wait in between.
+    const Acc *val_p = val ? val : unit_value<Acc>();
+    const int32_t vs = val ? 1 : 0;
+    const Acc *wv1_p = wv1 ? wv1 : unit_value<Acc>();
+    const int32_t w1s = wv1 ? 1 : 0;
+    const Acc *wv2_p = wv2 ? wv2 : unit_value<Acc>();
+    const int32_t w2s = wv2 ? 1 : 0;
+    const int32_t *perm_p = wperm ? wperm : zero_index();
+    const int32_t ps = wperm ? 1 : 0;
+    const bool partial = C < L * NV;  // some lanes own no vector of r (uniform)
+
+    // One batch of U entries from p0.  FULL: all U entries lie in the line.  Otherwise the
+    // entries past `end` read the last entry's index (one unconditional load) but load no
+    // row, and are left out of every sum and store.  Their row registers are left as they
+    // are, not zeroed: a zero write to a register that an in-flight load targets would
+    // force a wait for that load, serialising the batch.
+    auto run_batch = [&](int32_t p0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        int32_t j[U];
+        bool okv[U];
+        Acc w1[U], w2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
-            const bool ok = p < end;
-            j[u] = ok ? idx[p] : -1;
-            Acc base = (ok && val) ? val[p] : Acc(ok ? 1 : 0);
+            okv[u] = FULL || p < end;
+            const int32_t pc = okv[u] ? p : end - 1;
+            j[u] = idx[pc];
+            const Acc base = val_p[pc * vs];
             if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
-                const int32_t q = (ok && wperm) ? wperm[p] : p;
-                w1[u] = (ok && wv1) ? base * wv1[q] : base;
-                if constexpr (OP == OP_SPMM2) w2[u] = (ok && wv2) ? base * wv2[q] : base;
-                else w2[u] = Acc(0);
+                const int32_t q = perm_p[pc * ps] + pc * (1 - ps);
+                w1[u] = base * wv1_p[q * w1s];
+                w2[u] = (OP == OP_SPMM2) ? base * wv2_p[q * w2s] : Acc(0);
             } else {
                 w1[u] = base;
                 w2[u] = Acc(0);
             }
         }
-    };
-
-    int32_t j[U];
-    Acc w1[U], w2[U];
-    if (kPrefetch) load_batch(begin + gidx * U, j, w1, w2);
-    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
-        if (!kPrefetch) load_batch(p0, j, w1, w2);
         Raw<TG1, VW> g1[U][NV];
         Raw<TG2, VW> g2[kTwo ? U : 1][kTwo ? NV : 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool ok = j[u] >= 0;
-            const TG1 *row1 = G1 + (size_t)(ok ? j[u] : 0) * r;
+            const TG1 *row1 = G1 + (size_t)j[u] * r;
+            const TG2 *row2 = G2 + (size_t)j[u] * r;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                if (ok && act[v]) g1[u][v].load(row1 + off[v]);
-                else g1[u][v].zero();
-            }
-            if constexpr (kTwo) {
-                const TG2 *row2 = G2 + (size_t)(ok ? j[u] : 0) * r;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (ok && act[v]) g2[u][v].load(row2 + off[v]);
-                    else g2[u][v].zero();
+                const int o = act[v] ? off[v] : 0;  // idle lanes read a valid spot, zeroed below
+                if (FULL || okv[u]) {
+                    g1[u][v].load(row1 + o);
+                    if constexpr (kTwo) g2[u][v].load(row2 + o);
                 }
             }
         }
-
-        // with prefetching, the next batch's indices are requested while this batch's
-        // rows are still in flight
-        int32_t jn[U];
-        Acc w1n[U], w2n[U];
-        if (kPrefetch) load_batch(p0 + U * GPL, jn, w1n, w2n);
-
-        if constexpr (OP == OP_SPMM1) {
+        if (partial) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
+                    if (!act[v]) {
+                        g1[u][v].zero();
+                        if constexpr (kTwo) g2[u][v].zero();
+                    }
+        }
+
+        if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e));
-        } else if constexpr (OP == OP_SPMM2) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u) {
+                if (!FULL && !okv[u]) continue;
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int e = 0; e < VW; ++e)
-                        acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e)) + w2[u] * Acc(g2[u][v].get(e));
+                    for (int e = 0; e < VW; ++e) {
+                        if constexpr (OP == OP_SPMM2)
+                            acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e)) + w2[u] * Acc(g2[u][v].get(e));
+                        else
+                            acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e));
+                    }
+            }
         } else if constexpr (OP == OP_FUSED2) {
             Acc d1[U], d2[U];
 #pragma unroll
@@ -459,7 +470,15 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 d2[u] = group_sum<L>(d2[u]);
             }
 #pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    g1[u][v].pin();
+                    g2[u][v].pin();
+                }
+#pragma unroll
             for (int u = 0; u < U; ++u) {
+                if (!FULL && !okv[u]) continue;
                 const Acc c1 = w1[u] * d1[u], c2 = w1[u] * d2[u];
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
@@ -485,7 +504,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int32_t p = p0 + u;
-                    if (lane == (u % L) && p < end) {
+                    if (lane == (u % L) && okv[u]) {
                         const Acc res = w1[u] * d[u];
                         const int64_t q = o.operm ? o.operm[p] : p;
                         R[q] = (o.beta == 0.0) ? res : Acc(o.beta) * R[q] + res;
@@ -493,7 +512,12 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 }
             } else {
 #pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) g1[u][v].pin();
+#pragma unroll
                 for (int u = 0; u < U; ++u) {
+                    if (!FULL && !okv[u]) continue;
                     const Acc c = w1[u] * d[u];
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
@@ -502,14 +526,11 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 }
             }
         }
-        if (kPrefetch) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                j[u] = jn[u];
-                w1[u] = w1n[u];
-                w2[u] = w2n[u];
-            }
-        }
+    };
+
+    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
+        if (p0 + U <= end) run_batch(p0, std::true_type{});
+        else run_batch(p0, std::false_type{});
     }
 
     if constexpr (OP != OP_SDDMM) {

@@ -172,6 +172,32 @@ class Pattern:
             return self.csr if orient == C.FMM_CSR else self.csc
         return self._desc(orient, with_sched=False)
 
+    def set_variant(self, csr=None, csc=None):
+        """Batch depth class of each orientation (FMM_VARIANT_*; 0 = automatic)."""
+        if csr is not None:
+            self.csr.variant = int(csr)
+        if csc is not None:
+            self.csc.variant = int(csc)
+
+    @property
+    def variants(self):
+        return {"csr": self.csr.variant, "csc": self.csc.variant}
+
+    def autotune(self, A, B, dC, form="a"):
+        """Time the batch variants of FusedMMA (form "a") or FusedMMB ("b") forward and
+        adjoint on these operands and keep the fastest per orientation."""
+        r = A.shape[1]
+        dcode, odt = _common(self, A, B)
+        rows_out = self.m if form == "a" else self.n
+        C_out = torch.empty(rows_out, r, dtype=odt, device=self.device)
+        dA = torch.empty(self.m, r, dtype=odt, device=self.device)
+        dB = torch.empty(self.n, r, dtype=odt, device=self.device)
+        op = C.FMM_OP_FUSEDMM_A_BWD if form == "a" else C.FMM_OP_FUSEDMM_B_BWD
+        ws, wb = self.workspace(op, r, dcode)
+        C.call("fmm_autotune", op, ctypes.byref(self.csr), ctypes.byref(self.csc), _ptr(A), _ptr(B), _ptr(dC), r,
+               dcode, _ptr(C_out), _ptr(dA), _ptr(dB), _ptr(ws), wb, _stream())
+        return self.variants
+
     @property
     def schedules(self):
         return {"csr": self._csr_sched, "csc": self._csc_sched}

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(lib, n), n
         assert n in C.SIGNATURES, n
-    assert lib.fmm_abi_version() == 1
+    assert lib.fmm_abi_version() == 2
 
 
 def test_status_strings():
@@ -66,6 +66,9 @@ def test_argument_errors_forward():
     assert _fa(d, A=FAKE + 4) == -8                      # misaligned vector rows
     assert _fa(d, flags=5) == -2
     assert _fa(d, flags=C.FMM_UNFUSED, R=None) == -7     # unfused needs R workspace
+    d.variant = 4
+    assert _fa(d) == -2
+    d.variant = 0
     d.ptr = None
     assert _fa(d) == -1
 

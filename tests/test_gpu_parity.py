@@ -382,3 +382,45 @@ def test_shape_overrides_agree():
             gate(f"lanes={lanes} nv={nv}", host(Cg), ref, mag, TOL_F32)
     finally:
         F.set_tuning(0, 0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float64])
+def test_batch_variants_parity(dtype):
+    S32 = rmat(11, 8, seed=181)
+    S = S32 if dtype != torch.float64 else CsrPattern(S32.m, S32.n, S32.rowptr, S32.colidx,
+                                                        S32.val.astype(np.float64))
+    r = 64
+    A, B = _inputs(S, r, 182, dtype)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    Ga, Gb = dense_normal(S.m, r, 183, dtype=npdt), dense_normal(S.n, r, 184, dtype=npdt)
+    odt = torch.float64 if dtype == torch.float64 else torch.float32
+    P = _pattern(S, long_len=64, chunk=32)
+    Ad, Bd = _to_dev(A, dtype), _to_dev(B, dtype)
+    tol = TOL[dtype]
+    ref, mag = ref_fusedmm_a(S, A, B)
+    refb, magb = ref_fusedmm_b(S, A, B)
+    dA, dB, mA, mB = ref_fusedmm_a_backward(S, A, B, Ga)
+    eA, eB, nA, nB = ref_fusedmm_b_backward(S, A, B, Gb)
+    Rr, Rm = ref_sddmm(S, A, B)
+    for v in (1, 2, 3):
+        log(f"variant {v} dtype={dtype}")
+        P.set_variant(v, v)
+        for fused in (True, False):
+            Cg, R_ws = F.fusedmm_a_raw(P, Ad, Bd, fused=fused)
+            gate(f"v{v} FusedMMA fused={fused}", host(Cg), ref, mag, tol)
+            gA, gB = F.fusedmm_a_backward_raw(P, Ad, Bd, dev(Ga, odt), fused=fused, R_ws=R_ws)
+            gate(f"v{v} dA fused={fused}", host(gA), dA, mA, tol)
+            gate(f"v{v} dB fused={fused}", host(gB), dB, mB, tol)
+            Cb, Rb = F.fusedmm_b_raw(P, Ad, Bd, fused=fused)
+            gate(f"v{v} FusedMMB fused={fused}", host(Cb), refb, magb, tol)
+            gA, gB = F.fusedmm_b_backward_raw(P, Ad, Bd, dev(Gb, odt), fused=fused, R_ws=Rb)
+            gate(f"v{v} B dA fused={fused}", host(gA), eA, nA, tol)
+            gate(f"v{v} B dB fused={fused}", host(gB), eB, nB, tol)
+        gate(f"v{v} SDDMM", host(F.sddmm_raw(P, Ad, Bd)), Rr, Rm, tol)
+    P.set_variant(0, 0)
+    got = P.autotune(Ad, Bd, dev(Ga, odt), form="a")
+    assert got["csr"] in (1, 2, 3) and got["csc"] in (1, 2, 3)
+    Cg, _ = F.fusedmm_a_raw(P, Ad, Bd)
+    gate("autotuned FusedMMA", host(Cg), ref, mag, tol)
+    got = P.autotune(Ad, Bd, dev(Gb, odt), form="b")
+    assert got["csr"] in (1, 2, 3) and got["csc"] in (1, 2, 3)
