@@ -86,7 +86,9 @@ def cpu_baseline(w, target_s=15.0):
                       f"{t:.1f} s"}
 
 COPY_BYTES = 1 << 30
-SRC_GLOBS = ("paper_2203_07673_amd/csrc/*.hip", "paper_2203_07673_amd/csrc/*.hpp")
+# the sources that define the line kernels (their counters go stale when these change)
+SRC_GLOBS = ("paper_2203_07673_amd/csrc/fmm_lines.hpp", "paper_2203_07673_amd/csrc/fmm_launch.hpp",
+             "paper_2203_07673_amd/csrc/lines_*.hip")
 
 
 def source_hash():
@@ -389,22 +391,18 @@ def main():
     dom_bytes = kernel_bytes(dom, m, n, nnz, r, e)
     achieved = dom_bytes / (kt[dom] * 1e-3) / 1e9
     step_bytes = sum(kernel_bytes(k, m, n, nnz, r, e) for k in kinds)
-    op_prefix = {"fwd": "line_kernel<3, float, float, float, float,",
-                 "bwd_row": "line_kernel<3, float, float, float, float,",
-                 "bwd_col": "line_kernel<4, float, float, float, float,"}[dom]
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-    if os.path.exists(tf):
-        with open(tf) as fh:
-            keys = [k for k in json.load(fh)["kernels"] if k.startswith(op_prefix)]
-        if len(keys) == 1:
-            traffic = load_traffic(args.workload, keys[0])
+    # exact instantiation of the dominant kernel, to look up its counter data
+    from paper_2203_07673_amd import _capi as CA
+    orient = CA.FMM_CSC if dom == "bwd_col" else CA.FMM_CSR
+    L, NV, VW, U = P.launch_shape(orient, dom == "bwd_col", r, CA.FMM_F32)
+    op = 4 if dom == "bwd_col" else 3
+    kernel_key = f"line_kernel<{op}, float, float, float, float, {L}, {NV}, {VW}, {U}>"
+    traffic = load_traffic(args.workload, kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "kernel": {"fwd": "FusedMMA forward (line_kernel op 3)",
-                           "bwd_row": "adjoint row pass dA (line_kernel op 3)",
-                           "bwd_col": "adjoint column pass dB (line_kernel op 4)"}[dom],
+                "kernel": {"fwd": "FusedMMA forward", "bwd_row": "adjoint row pass dA",
+                           "bwd_col": "adjoint column pass dB"}[dom] + f" ({kernel_key})",
                 "kernel_ms": round(kt[dom], 4), "bytes_per_launch": int(dom_bytes),
                 "bytes_model": "gather (each stored entry fetches its dense row(s))",
                 "frac_compulsory_bytes": round(kernel_bytes_min(dom, m, n, nnz, r, e) / (kt[dom] * 1e-3) / 1e9

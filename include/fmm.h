@@ -138,6 +138,15 @@ fmm_status fmm_device_info(int32_t *num_cu, char *arch, int32_t arch_len);
  */
 fmm_status fmm_set_tuning(int32_t lanes, int32_t nv);
 
+/*
+ * The line-kernel configuration a call on S would launch (for profiling and tests):
+ * lanes per line, 16-byte vectors per lane, elements per vector and entries per batch,
+ * for the one-row passes (two_row = 0: SDDMM, SpMM, fused forward, dA/dB of the same
+ * orientation) or the two-row adjoint pass (two_row = 1).  Host-only; no device work.
+ */
+fmm_status fmm_launch_shape(const fmm_sparse *S, int32_t two_row, int32_t r, int32_t dtype, int32_t *lanes,
+                            int32_t *nv, int32_t *vw, int32_t *unroll);
+
 /* ---------------------------------------------------------------- pattern prep */
 
 /*

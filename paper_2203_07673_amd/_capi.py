@@ -116,6 +116,8 @@ SIGNATURES = {
     "fmm_sddmm_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_a_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
     "fmm_spmm_b_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P],
+    "fmm_launch_shape": [_SP, _I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                         ctypes.POINTER(_I32)],
     "fmm_autotune": [_I32, _SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
     "fmm_batch_plan_create": [ctypes.POINTER(fmm_batch_graph), _I32, _I32, _I32, _I32, ctypes.POINTER(_P)],
     "fmm_batch_autotune": [_P, _P],

@@ -755,6 +755,30 @@ fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
     return FMM_OK;
 }
 
+// ---------------------------------------------------------------- launch introspection
+
+fmm_status fmm_launch_shape(const fmm_sparse *S, int32_t two_row, int32_t r, int32_t dtype, int32_t *lanes, int32_t *nv,
+                            int32_t *vw, int32_t *unroll)
+{
+    FMM_TRY(check_sparse(S, -1));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    if (!lanes || !nv || !vw || !unroll) return FMM_ERR_NULL;
+    // the vector width follows the narrowest operand: bfloat16 storage gives 8, else 16 / element
+    const int vwv = k.path == PATH_BF16 ? 8 : k.path == PATH_F64 ? 2 : 4;
+    const int w = (r % vwv) == 0 ? vwv : 1;
+    const Shape hs{tuning().lanes, tuning().nv};
+    const Shape sh = shape_supported(hs, r, w) ? hs : default_shape(r, w);
+    const int cls = unroll_class(S);
+    const int one = cls == 1 ? 8 : cls == 2 ? 4 : 2;
+    int u = (two_row ? one / 2 : one) / sh.NV;
+    *lanes = sh.L;
+    *nv = sh.NV;
+    *vw = w;
+    *unroll = u < 1 ? 1 : u;
+    return FMM_OK;
+}
+
 // ---------------------------------------------------------------- variant autotuning
 
 fmm_status fmm_autotune(int32_t op, fmm_sparse *S_csr, fmm_sparse *S_csc, const void *A, const void *B, const void *dC,

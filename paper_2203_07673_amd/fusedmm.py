@@ -179,6 +179,14 @@ class Pattern:
         if csc is not None:
             self.csc.variant = int(csc)
 
+    def launch_shape(self, orient, two_row, r, dcode):
+        """(lanes, vectors per lane, elements per vector, entries per batch) of the line
+        kernel a call on this orientation launches."""
+        vals = [ctypes.c_int32(0) for _ in range(4)]
+        C.call("fmm_launch_shape", ctypes.byref(self.descriptor(orient)), int(two_row), r, dcode,
+               *[ctypes.byref(v) for v in vals])
+        return tuple(v.value for v in vals)
+
     @property
     def variants(self):
         return {"csr": self.csr.variant, "csc": self.csc.variant}
