@@ -12,7 +12,8 @@ composite operations from them, exactly as the paper defines them (Section II):
     FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A)
 
 and the adjoints, which the paper does not give.  They are derived here from
-R = S * P with P = A B^T (the derivation is repeated in each docstring).
+R = S * P with P = A B^T (the derivation is repeated in each docstring).  It also
+holds the graph-attention variant of the sampled product (Section VI-E).
 
 Every input is promoted exactly to float64 before use.  A "pattern" argument is
 any object with attributes ``m, n, rowptr, colidx, val`` (canonical CSR).
@@ -40,7 +41,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-                               "-std=c11", "-Wall", "-o", tmp, _SRC])
+                               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -57,6 +58,10 @@ def _load():
             lib.oracle_spmm_b.argtypes = [i64, i64, i64, p, p, p, p, p]
             lib.oracle_csr_to_csc.argtypes = [i64, i64, p, p, p, p, p, p, p]
             lib.oracle_num_threads.restype = ctypes.c_int
+            lib.oracle_gat_scores.argtypes = [i64, i64, p, p, p, p, p]
+            lib.oracle_gat_scores.restype = None
+            lib.oracle_gat_edges.argtypes = [i64, p, p, p, p, p, ctypes.c_double, ctypes.c_int, p]
+            lib.oracle_gat_edges.restype = None
             for f in ("oracle_sddmm", "oracle_spmm_a", "oracle_spmm_b", "oracle_csr_to_csc"):
                 getattr(lib, f).restype = None
             _lib = lib
@@ -282,3 +287,40 @@ def bf16_round(x):
     nan = np.isnan(x)
     out[nan] = x[nan]
     return out
+
+
+# ----------------------------------------------------------------------------------
+# Graph attention (Section VI-E): S' = LeakyReLU(S * (H ._GAT H^T)), optionally
+# row-softmax normalised, then the aggregation S' . H
+# ----------------------------------------------------------------------------------
+
+def gat_scores(H, a1, a2):
+    """s = H a1, t = H a2: the two halves of a^T (H_i || H_j) = s_i + t_j."""
+    lib = _load()
+    H, a1, a2 = _f64(H), _f64(a1), _f64(a2)
+    n, r = H.shape
+    assert a1.shape == (r,) and a2.shape == (r,)
+    s = np.empty(n, dtype=np.float64)
+    t = np.empty(n, dtype=np.float64)
+    lib.oracle_gat_scores(n, r, _ptr(H), _ptr(a1), _ptr(a2), _ptr(s), _ptr(t))
+    return s, t
+
+
+def gat_edges(S, s, t, slope=0.2, softmax=True, use_val=True):
+    """Edge weights in CSR order: LeakyReLU(S_ij (s_i + t_j)), row-softmaxed if asked."""
+    lib = _load()
+    s, t = _f64(s), _f64(t)
+    v = _f64(S.val) if use_val and S.val is not None else None
+    w = np.empty(S.colidx.shape[0], dtype=np.float64)
+    rp, ci = _i32(S.rowptr), _i32(S.colidx)
+    lib.oracle_gat_edges(S.m, _ptr(rp), _ptr(ci), _ptr(v), _ptr(s), _ptr(t), float(slope), int(bool(softmax)),
+                         _ptr(w))
+    return w
+
+
+def gat_forward(S, H, a1, a2, slope=0.2, softmax=True, use_val=True, rows=None):
+    """One attention head: out = S' . H with S' the (row-softmaxed) LeakyReLU edge values.
+    H is n x r with n = S.m = S.n (a square graph)."""
+    s, t = gat_scores(H, a1, a2)
+    w = gat_edges(S, s, t, slope, softmax, use_val)
+    return spmm_a(S, w, H, rows=rows)

@@ -30,6 +30,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 /* Rows to visit: rows[t] for t < nrows, or every row 0..m-1 when rows == NULL. */
 static inline int64_t pick_row(const int64_t *rows, int64_t t) { return rows ? rows[t] : t; }
@@ -146,4 +147,54 @@ int oracle_num_threads(void)
         }
     }
     return t;
+}
+
+/*
+ * Graph attention edge scores (Section VI-E): the attention product of row i and row j
+ * is a^T (H_i: || H_j:) = a1 . H_i + a2 . H_j, with a = (a1 || a2).  Per node:
+ *   s[i] = sum_k a1[k] H[i,k],   t[i] = sum_k a2[k] H[i,k].
+ */
+void oracle_gat_scores(int64_t n, int64_t r, const double *H, const double *a1, const double *a2, double *s, double *t)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x = 0.0, y = 0.0;
+        for (int64_t k = 0; k < r; ++k) {
+            x += a1[k] * H[i * r + k];
+            y += a2[k] * H[i * r + k];
+        }
+        s[i] = x;
+        t[i] = y;
+    }
+}
+
+/*
+ * Edge values S'_ij = LeakyReLU(S_ij (s_i + t_j)) at the stored entries (Section VI-E:
+ * the sampled attention product followed by LeakyReLU), and, when softmax != 0, the
+ * softmax of each row's values over its stored entries:
+ *   w[p] = exp(e[p] - max_row) / sum_{q in row} exp(e[q] - max_row).
+ * val == NULL means a 0/1 adjacency (every stored value 1).
+ */
+void oracle_gat_edges(int64_t m, const int32_t *rowptr, const int32_t *colidx, const double *val, const double *s,
+                      const double *t, double slope, int softmax, double *w)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t b = rowptr[i], e = rowptr[i + 1];
+        for (int64_t p = b; p < e; ++p) {
+            const double x = (val ? val[p] : 1.0) * (s[i] + t[colidx[p]]);
+            w[p] = x >= 0.0 ? x : slope * x;
+        }
+        if (softmax && e > b) {
+            double mx = w[b];
+            for (int64_t p = b + 1; p < e; ++p)
+                if (w[p] > mx) mx = w[p];
+            double sum = 0.0;
+            for (int64_t p = b; p < e; ++p) {
+                w[p] = exp(w[p] - mx);
+                sum += w[p];
+            }
+            for (int64_t p = b; p < e; ++p) w[p] /= sum;
+        }
+    }
 }

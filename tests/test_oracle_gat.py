@@ -1,0 +1,85 @@
+"""Pins for the graph-attention oracle (Section VI-E): dense brute force in numpy,
+torch's LeakyReLU and softmax on the dense masked matrix, and closed forms."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import er_exact_degree, tiny_case, rmat, dense_normal
+
+
+def _dense(S):
+    D = np.zeros((S.m, S.n))
+    M = np.zeros((S.m, S.n), dtype=bool)
+    rows = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    D[rows, S.colidx] = S.val
+    M[rows, S.colidx] = True
+    return D, M
+
+
+@pytest.mark.parametrize("softmax", [True, False])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gat_dense_bruteforce_numpy(softmax, seed):
+    case = tiny_case(23, 23, 6, 0.3, seed=300 + seed)
+    S, H = case["S"], case["A"]
+    rng = np.random.default_rng(seed)
+    a1, a2 = rng.standard_normal(6), rng.standard_normal(6)
+    D, M = _dense(S)
+    s, t = H @ a1, H @ a2
+    X = D * (s[:, None] + t[None, :])
+    E = np.where(X >= 0, X, 0.2 * X)
+    if softmax:
+        Em = np.where(M, E, -np.inf)
+        mx = np.max(Em, axis=1, keepdims=True)
+        mx = np.where(np.isfinite(mx), mx, 0)
+        P = np.where(M, np.exp(Em - mx), 0)
+        den = P.sum(axis=1, keepdims=True)
+        W = np.where(den > 0, P / np.where(den > 0, den, 1), 0)
+    else:
+        W = np.where(M, E, 0)
+    got = oracle.gat_forward(S, H, a1, a2, slope=0.2, softmax=softmax)
+    assert np.max(np.abs(got - W @ H)) <= 1e-12 * (1 + np.abs(W @ H).max())
+
+
+def test_gat_vs_torch_leaky_relu_and_softmax():
+    case = tiny_case(17, 17, 5, 0.4, seed=310)
+    S, H = case["S"], case["A"]
+    rng = np.random.default_rng(311)
+    a1, a2 = rng.standard_normal(5), rng.standard_normal(5)
+    D, M = _dense(S)
+    Ht = torch.tensor(H)
+    s = Ht @ torch.tensor(a1)
+    t = Ht @ torch.tensor(a2)
+    E = torch.nn.functional.leaky_relu(torch.tensor(D) * (s[:, None] + t[None, :]), negative_slope=0.3)
+    E = E.masked_fill(~torch.tensor(M), float("-inf"))
+    W = torch.softmax(E, dim=1)
+    W = torch.nan_to_num(W, nan=0.0)  # rows without entries
+    ref = (W @ Ht).numpy()
+    got = oracle.gat_forward(S, H, a1, a2, slope=0.3, softmax=True)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * (1 + np.abs(ref).max())
+
+
+def test_gat_zero_attention_is_neighbour_mean():
+    S = er_exact_degree(200, 200, 7, seed=312, val_dtype=np.float64)
+    H = dense_normal(200, 9, 313, dtype=np.float64)
+    z = np.zeros(9)
+    got = oracle.gat_forward(S, H, z, z, softmax=True)
+    ref = np.stack([H[S.colidx[S.rowptr[i]:S.rowptr[i + 1]]].mean(axis=0) for i in range(200)])
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+def test_gat_single_neighbour_copies_row_and_weights_sum_to_one():
+    n = 50
+    perm = np.random.default_rng(314).permutation(n)
+    from types import SimpleNamespace
+    S = SimpleNamespace(m=n, n=n, rowptr=np.arange(n + 1, dtype=np.int32), colidx=perm.astype(np.int32),
+                        val=np.ones(n))
+    H = dense_normal(n, 4, 315, dtype=np.float64)
+    a1, a2 = dense_normal(1, 4, 316, dtype=np.float64)[0], dense_normal(1, 4, 317, dtype=np.float64)[0]
+    assert np.array_equal(oracle.gat_forward(S, H, a1, a2, softmax=True), H[perm])
+    S2 = rmat(9, 8, seed=318, val_dtype=np.float64)
+    H2 = dense_normal(S2.m, 4, 319, dtype=np.float64)
+    s, t = oracle.gat_scores(H2, a1, a2)
+    w = oracle.gat_edges(S2, s, t, softmax=True)
+    sums = np.add.reduceat(w, S2.rowptr[:-1][np.diff(S2.rowptr) > 0])
+    assert np.allclose(sums, 1.0, atol=1e-14, rtol=0)
