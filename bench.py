@@ -287,6 +287,54 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_gat(args):
+    """Graph-attention forward (Section VI-E): 4 heads of r = 128 on the R-MAT scale 20
+    graph, softmax-normalised; fused one-pass head vs the unfused sequence (edge values
+    written to memory, then an SpMM)."""
+    import torch
+
+    import paper_2203_07673_amd as F
+    from workloads import dense_normal, workload
+
+    w = workload("rmat20_ef16_r64")
+    S = w["S"]
+    r, heads = 128, 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = F.Pattern.from_csr(S, device=dev)
+    Hs = [torch.from_numpy(dense_normal(S.n, r, 500 + h)).to(dev) for h in range(heads)]
+    a = [(torch.from_numpy(dense_normal(1, r, 600 + h, sigma=r ** -0.5)[0]).to(dev),
+          torch.from_numpy(dense_normal(1, r, 700 + h, sigma=r ** -0.5)[0]).to(dev)) for h in range(heads)]
+    outs = [torch.empty(S.m, r, device=dev) for _ in range(heads)]
+
+    def step(Hl):
+        for h in range(heads):
+            F.gat_forward(P, Hl[h], a[h][0], a[h][1], softmax=True, out=outs[h])
+
+    def timeit(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t32 = timeit(lambda: step(Hs), args.steps, args.warmup)
+    H16 = [F.to_bf16(x) for x in Hs]
+    t16 = timeit(lambda: step(H16), args.steps, args.warmup)
+    # gather model per head: each stored entry fetches its feature row and t_j; rows read H once
+    # for the scores and write out once
+    nnz, n = S.nnz, S.n
+    bytes32 = heads * (nnz * (4 * r + 12) + n * (4 * r + 4 * r + 12))
+    out = {"metric": "graph-attention forward (4 heads, softmax) ms", "workload": "gat_rmat20_r128_h4",
+           "nnz": nnz, "n": n, "r": r, "heads": heads,
+           "fused_f32_ms": round(t32 * 1e3, 4), "fused_bf16_ms": round(t16 * 1e3, 4),
+           "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +364,9 @@ def main():
 
     if args.workload == "batch256_r64":
         run_batch(args)
+        return
+    if args.workload == "gat_rmat20_r128_h4":
+        run_gat(args)
         return
 
     import torch

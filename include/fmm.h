@@ -328,6 +328,34 @@ fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
                                void *dA, void *ws, size_t ws_bytes, hipStream_t stream);
 
 
+/* ---------------------------------------------------------------- graph attention */
+
+/*
+ * Graph-attention variant of the sampled product (Section VI-E): one attention head on a
+ * square graph S (n x n CSR, values S_ij or NULL for a 0/1 adjacency) with node features
+ * H (n x r, H = A W computed by the caller) and attention vector a = (a1 || a2):
+ *
+ *   score_ij = a^T (H_i || H_j) = s_i + t_j,   s = H a1,  t = H a2      (fmm_gat_scores)
+ *   e_ij     = LeakyReLU(S_ij * score_ij)  (negative_slope for x < 0)
+ *   w_ij     = e_ij, or with FMM_GAT_SOFTMAX the softmax of e over the stored entries of
+ *              row i (the softmax regularisation of learned edge weights)
+ *   out_i    = sum_j w_ij H_j                                            (fmm_gat_forward)
+ *
+ * The forward is one pass per row: edge values never reach memory (with the softmax the
+ * running maximum and normaliser are kept with the partial sum and rescaled as the
+ * maximum grows).  Rows with no stored entry give 0.  dtype is H's storage (FMM_F32,
+ * FMM_BF16, FMM_F64); a1, a2, s, t, out and S's values are float32 (float64 for
+ * FMM_F64).  A split schedule on S is honoured; it then needs a workspace of
+ * fmm_gat_workspace() bytes.  Multi-head attention is one call per head.
+ */
+#define FMM_GAT_SOFTMAX 1
+fmm_status fmm_gat_scores(const void *H, int32_t n, int32_t r, int32_t dtype, const void *a1, const void *a2,
+                          void *s, void *t, hipStream_t stream);
+fmm_status fmm_gat_workspace(const fmm_sparse *S, int32_t r, int32_t dtype, size_t *bytes);
+fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, const void *H, int32_t r, int32_t dtype,
+                           double negative_slope, int32_t flags, void *out, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
 /* ---------------------------------------------------------------- batched graphs */
 
 /*

@@ -15,6 +15,8 @@ from .fusedmm import (  # noqa: F401
     fusedmm_b,
     fusedmm_b_backward_raw,
     fusedmm_b_raw,
+    gat_forward,
+    gat_scores,
     sddmm,
     sddmm_raw,
     set_tuning,

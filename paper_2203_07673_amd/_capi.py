@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "FMM_OK", -1: "FMM_ERR_NULL", -2: "FMM_ERR_DIM", -3: "FMM_ERR
                 -5: "FMM_ERR_INDEX", -6: "FMM_ERR_NONCANONICAL", -7: "FMM_ERR_WORKSPACE",
                 -8: "FMM_ERR_UNSUPPORTED", -9: "FMM_ERR_HIP", -10: "FMM_ERR_STATE"}
 FMM_BATCH_FWD, FMM_BATCH_BWD = 1, 2
+FMM_GAT_SOFTMAX = 1
 
 
 class fmm_sparse(ctypes.Structure):
@@ -119,6 +120,9 @@ SIGNATURES = {
     "fmm_launch_shape": [_SP, _I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                          ctypes.POINTER(_I32)],
     "fmm_autotune": [_I32, _SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
+    "fmm_gat_scores": [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P],
+    "fmm_gat_workspace": [_SP, _I32, _I32, ctypes.POINTER(_SZ)],
+    "fmm_gat_forward": [_SP, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _SZ, _P],
     "fmm_batch_plan_create": [ctypes.POINTER(fmm_batch_graph), _I32, _I32, _I32, _I32, ctypes.POINTER(_P)],
     "fmm_batch_autotune": [_P, _P],
     "fmm_batch_run": [_P, _P],

@@ -24,7 +24,7 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan"]
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward"]
 
 DEFAULT_LONG_LEN = 256
 DEFAULT_CHUNK = 256
@@ -462,6 +462,43 @@ def spmm_a(P: Pattern, B, w=None):
 def spmm_b(P: Pattern, A, w=None):
     """S^T A, or W^T A where W has S's pattern and stored values w (CSR order)."""
     return _SpMMB.apply(P, A, w)
+
+
+def gat_scores(H, a1, a2):
+    """s = H a1, t = H a2 (the two halves of the attention score a^T (H_i || H_j))."""
+    n, r = H.shape
+    dcode = dtype_code(H)
+    odt = _out_dtype(dcode)
+    if a1.dtype != odt or a2.dtype != odt:
+        raise TypeError(f"attention vectors must be {odt}")
+    s = torch.empty(n, dtype=odt, device=H.device)
+    t = torch.empty(n, dtype=odt, device=H.device)
+    C.call("fmm_gat_scores", _ptr(H.contiguous()), n, r, dcode, _ptr(a1.contiguous()), _ptr(a2.contiguous()),
+           _ptr(s), _ptr(t), _stream())
+    return s, t
+
+
+def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=None):
+    """One graph-attention head (Section VI-E): out_i = sum_j w_ij H_j with
+    w = LeakyReLU(S_ij (a1.H_i + a2.H_j)), row-softmaxed when ``softmax``."""
+    if P.m != P.n:
+        raise ValueError("graph attention needs a square pattern")
+    r = H.shape[1]
+    _check_dense("H", H, P.n, r, P.device)
+    dcode, odt = _common(P, H, None)
+    s, t = gat_scores(H, a1, a2)
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    nb = ctypes.c_size_t(0)
+    C.call("fmm_gat_workspace", ctypes.byref(P.csr), r, dcode, ctypes.byref(nb))
+    ws = None
+    if nb.value:
+        ws = P._ws_cache.get(("gat", nb.value))
+        if ws is None:
+            ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
+            P._ws_cache[("gat", nb.value)] = ws
+    C.call("fmm_gat_forward", ctypes.byref(P.csr), _ptr(s), _ptr(t), _ptr(H), r, dcode, float(negative_slope),
+           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(ws), nb.value, _stream())
+    return out
 
 
 def to_bf16(x: torch.Tensor) -> torch.Tensor:

@@ -1,0 +1,123 @@
+"""GPU parity of the graph-attention head (Section VI-E) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_07673_amd as F
+from tests.gates import TOL_BF16, TOL_F32, TOL_F64
+from tests.gpu_helpers import dev, gate, host, log
+from workloads import CsrPattern, dense_normal, er_exact_degree, rmat, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: TOL_F32, torch.bfloat16: TOL_BF16, torch.float64: TOL_F64}
+
+
+def _ref(S, H, a1, a2, slope, softmax, rows=None):
+    """Oracle output and its magnitude companion.
+
+    With the softmax the weights are positive and sum to 1, and the score rounding
+    error moves each weight by a relative amount: sum_j w_ij |H_j| bounds the error.
+    Without it the weight is the score itself, whose rounding error is relative to
+    |S_ij| (|a1|.|H_i| + |a2|.|H_j|), not to the (possibly cancelled) score: the
+    companion is sum_j |S_ij| (|a1|.|H_i| + |a2|.|H_j|) |H_j|."""
+    s, t = oracle.gat_scores(H, a1, a2)
+    w = oracle.gat_edges(S, s, t, slope, softmax)
+    ref = oracle.spmm_a(S, w, H, rows=rows)
+    if softmax:
+        return ref, oracle.spmm_a(S, np.abs(w), np.abs(H), rows=rows)
+    ms, mt = oracle.gat_scores(np.abs(H), np.abs(a1), np.abs(a2))
+    rowsof = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    wm = np.abs(np.asarray(S.val, np.float64)) * (ms[rowsof] + mt[S.colidx])
+    return ref, oracle.spmm_a(S, wm, np.abs(H), rows=rows)
+
+
+CASES = [
+    ("er_r64", lambda: er_exact_degree(700, 700, 12, seed=401), 64, False),
+    ("er_r3", lambda: er_exact_degree(300, 300, 9, seed=402), 3, False),
+    ("rmat_r128_split", lambda: rmat(11, 8, seed=403), 128, True),
+    ("rmat_r8", lambda: rmat(10, 16, seed=404), 8, True),
+]
+
+
+@pytest.mark.parametrize("case", [c[0] for c in CASES])
+def test_gat_forward_parity(case):
+    _, build, r, split = [c for c in CASES if c[0] == case][0]
+    S32 = build()
+    for dtype in (torch.float32, torch.float64, torch.bfloat16):
+        if dtype == torch.bfloat16 and r % 8:
+            continue
+        npdt = np.float64 if dtype == torch.float64 else np.float32
+        S = S32 if dtype != torch.float64 else CsrPattern(S32.m, S32.n, S32.rowptr, S32.colidx,
+                                                            S32.val.astype(np.float64))
+        H = dense_normal(S.n, r, 410, dtype=npdt)
+        a1 = dense_normal(1, r, 411, sigma=r ** -0.5, dtype=npdt)[0]
+        a2 = dense_normal(1, r, 412, sigma=r ** -0.5, dtype=npdt)[0]
+        odt = torch.float64 if dtype == torch.float64 else torch.float32
+        P = F.Pattern.from_csr(S, long_len=64 if split else 1 << 30, chunk=32 if split else 1 << 30, split=split)
+        if split:
+            assert P.schedules["csr"] is not None
+        Hd = F.to_bf16(dev(H)) if dtype == torch.bfloat16 else dev(H, dtype)
+        Hq = oracle.bf16_round(H) if dtype == torch.bfloat16 else H
+        a1d, a2d = dev(a1, odt), dev(a2, odt)
+        s, t = F.gat_scores(Hd, a1d, a2d)
+        es, et = oracle.gat_scores(Hq, a1, a2)
+        ms, mt = oracle.gat_scores(np.abs(Hq), np.abs(a1), np.abs(a2))
+        gate(f"{case} scores s {dtype}", host(s), es, ms, TOL_F64 if dtype == torch.float64 else TOL_F32)
+        gate(f"{case} scores t {dtype}", host(t), et, mt, TOL_F64 if dtype == torch.float64 else TOL_F32)
+        for softmax in (True, False):
+            log(f"gat {case} dtype={dtype} softmax={softmax}")
+            out = host(F.gat_forward(P, Hd, a1d, a2d, negative_slope=0.2, softmax=softmax))
+            if dtype == torch.bfloat16:
+                # bf16 storage moves the scores themselves by up to u * sum |a||H|, which the
+                # softmax turns into relative weight changes of that size: gate the GPU against
+                # the oracle on the same rounded features (accumulation error only), and keep
+                # only a sanity bound against the unrounded ones.
+                refq, magq = _ref(S, Hq, a1, a2, 0.2, softmax)
+                gate(f"{case} gat bf16-rounded softmax={softmax}", out, refq, magq, TOL_F32)
+                ref, mag = _ref(S, H, a1, a2, 0.2, softmax)
+                gate(f"{case} gat bf16 vs unrounded softmax={softmax}", out, ref, mag, 0.1)
+            else:
+                ref, mag = _ref(S, H, a1, a2, 0.2, softmax)
+                gate(f"{case} gat {dtype} softmax={softmax}", out, ref, mag, TOL[dtype])
+
+
+def test_gat_closed_forms_on_gpu():
+    S = er_exact_degree(300, 300, 7, seed=420)
+    H = dense_normal(300, 16, 421)
+    log("gat closed forms")
+    P = F.Pattern.from_csr(S)
+    z = torch.zeros(16, device="cuda")
+    out = host(F.gat_forward(P, dev(H), z, z, softmax=True))
+    ref = np.stack([H[S.colidx[S.rowptr[i]:S.rowptr[i + 1]]].astype(np.float64).mean(axis=0) for i in range(300)])
+    assert np.max(np.abs(out - ref)) <= 1e-5 * (1 + np.abs(ref).max())
+    # a row with no stored entries gives exactly 0
+    rp = np.array([0, 0, 2, 3], np.int32)
+    ci = np.array([0, 2, 1], np.int32)
+    S0 = CsrPattern(3, 3, rp, ci, np.ones(3, np.float32))
+    P0 = F.Pattern.from_csr(S0)
+    H0 = dense_normal(3, 8, 422)
+    o0 = host(F.gat_forward(P0, dev(H0), torch.ones(8, device="cuda"), torch.ones(8, device="cuda")))
+    assert np.all(o0[0] == 0)
+
+
+@pytest.mark.timeout(600)
+def test_gat_rmat20_r128_sampled():
+    w = workload("rmat20_ef16_r64")
+    S = w["S"]
+    r = 128
+    H = dense_normal(S.n, r, 430)
+    a1 = dense_normal(1, r, 431, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 432, sigma=r ** -0.5)[0]
+    log(f"gat rmat20 r=128 nnz={S.nnz}")
+    P = F.Pattern.from_csr(S)
+    lens = np.diff(S.rowptr.astype(np.int64))
+    rows = np.unique(np.concatenate([np.random.default_rng(433).choice(S.m, 2048, replace=False),
+                                     np.argsort(lens)[-16:], np.flatnonzero(lens == 0)[:8]]))
+    for dtype in (torch.float32, torch.bfloat16):
+        Hd = F.to_bf16(dev(H)) if dtype == torch.bfloat16 else dev(H)
+        out = F.gat_forward(P, Hd, dev(a1), dev(a2), softmax=True)
+        Hq = oracle.bf16_round(H) if dtype == torch.bfloat16 else H
+        ref, mag = _ref(S, Hq, a1, a2, 0.2, True, rows=rows)
+        gate(f"rmat20 gat {dtype}", host(out[torch.from_numpy(rows).cuda()]), ref, mag, TOL_F32)
