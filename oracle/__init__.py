@@ -324,3 +324,47 @@ def gat_forward(S, H, a1, a2, slope=0.2, softmax=True, use_val=True, rows=None):
     s, t = gat_scores(H, a1, a2)
     w = gat_edges(S, s, t, slope, softmax, use_val)
     return spmm_a(S, w, H, rows=rows)
+
+
+# ----------------------------------------------------------------------------------
+# Alternating least squares (Section VI-E): batched CG on the per-line normal equations
+# ----------------------------------------------------------------------------------
+
+def gram_apply(S, X, F):
+    """Per line i of S's pattern: sum_j <X_i, F_j> F_j (S's values ignored)."""
+    return spmm_a(S, sddmm(S, X, F, val=None), F)
+
+
+def _rowdot(X, Y):
+    return np.einsum("ij,ij->i", X, Y)
+
+
+def cg_lines(S, F, rhs, lam, iters, X0):
+    """Conjugate gradients, run for every line of S at once, on
+    (sum_{j in line} F_j F_j^T + lam I) x = rhs_line, starting from X0.  Each line runs the
+    textbook recurrence (residual r, direction p, alpha = r.r / p.Mp, beta = r'.r' / r.r);
+    a line whose residual or curvature is zero keeps its iterate."""
+    X = _f64(X0).copy()
+    rhs = _f64(rhs)
+    F = _f64(F)
+    R = rhs - (gram_apply(S, X, F) + lam * X)
+    P = R.copy()
+    rr = _rowdot(R, R)
+    for _ in range(iters):
+        MP = gram_apply(S, P, F) + lam * P
+        pq = _rowdot(P, MP)
+        ok = (rr > 0) & (pq > 0)
+        alpha = np.where(ok, rr / np.where(ok, pq, 1.0), 0.0)
+        X += alpha[:, None] * P
+        R -= alpha[:, None] * MP
+        rrn = _rowdot(R, R)
+        beta = np.where(rr > 0, rrn / np.where(rr > 0, rr, 1.0), 0.0)
+        P = R + beta[:, None] * P
+        rr = rrn
+    return X
+
+
+def als_residual(S, A, B):
+    """sum over stored entries of (S_ij - <A_i, B_j>)^2, S's values being the observations."""
+    pred = sddmm(S, A, B, val=None)
+    return float(np.sum((_f64(S.val) - pred) ** 2))
