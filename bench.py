@@ -335,6 +335,50 @@ def run_gat(args):
     print(json.dumps(out), flush=True)
 
 
+def run_als(args):
+    """ALS application (Section VI-E): one sweep = 10 batched CG steps for A, then 10 for
+    B (the paper's 20 CG iterations), each step's query vectors from one FusedMM-shaped
+    pass; observations are a noisy rank-128 product on an ER pattern (2^20 x 2^20, 32 per
+    row)."""
+    import torch
+
+    import paper_2203_07673_amd as F
+    from workloads import CsrPattern, dense_normal, er_exact_degree
+
+    m = n = 1 << 20
+    d, r = 32, 128
+    S = er_exact_degree(m, n, d, seed=21)
+    At = dense_normal(m, r, 22, sigma=r ** -0.5)
+    Bt = dense_normal(n, r, 23, sigma=r ** -0.5)
+    rows = np.repeat(np.arange(m), d)
+    obs = np.empty(S.nnz, np.float32)
+    for b0 in range(0, S.nnz, 1 << 22):
+        b1 = min(S.nnz, b0 + (1 << 22))
+        obs[b0:b1] = np.einsum("ij,ij->i", At[rows[b0:b1]], Bt[S.colidx[b0:b1]])
+    obs += np.float32(0.01) * np.random.default_rng(24).standard_normal(S.nnz, dtype=np.float32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = F.Pattern.from_csr(CsrPattern(m, n, S.rowptr, S.colidx, obs), device=dev)
+    A = torch.from_numpy(dense_normal(m, r, 25, sigma=0.1)).to(dev)
+    B = torch.from_numpy(dense_normal(n, r, 26, sigma=0.1)).to(dev)
+    loss0 = float(F.als_residual(P, A, B))
+    F.als_sweep(P, A, B, 1e-3, 10)  # warm-up sweep
+    torch.cuda.synchronize()
+    sweeps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        F.als_sweep(P, A, B, 1e-3, 10)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / sweeps
+    loss = float(F.als_residual(P, A, B))
+    # per sweep: 2 x 11 Gram passes (4 r nnz flops each) + 2 right-hand-side SpMMs (2 r nnz)
+    flops = 2 * (11 * 4 * r * S.nnz + 2 * r * S.nnz)
+    out = {"metric": "ALS sweep (20 batched CG iterations) ms", "workload": "als_er1m_d32_r128",
+           "nnz": S.nnz, "r": r, "ms_per_sweep": round(t * 1e3, 3), "gflops": round(flops / t / 1e9, 1),
+           "loss_start": loss0, "loss_after": loss, "sweeps_timed": sweeps}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +411,9 @@ def main():
         return
     if args.workload == "gat_rmat20_r128_h4":
         run_gat(args)
+        return
+    if args.workload == "als_er1m_d32_r128":
+        run_als(args)
         return
 
     import torch

@@ -356,6 +356,40 @@ fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, co
                            double negative_slope, int32_t flags, void *out, void *ws, size_t ws_bytes,
                            hipStream_t stream);
 
+/* ---------------------------------------------------------------- alternating least squares */
+
+/*
+ * Batched conjugate gradients for the per-line least-squares problems of alternating
+ * least squares on observed entries (Section VI-E).  For every major line x of S (a row
+ * of A when S is the CSR and F = B; a row of B when S is the stored transpose and F = A):
+ *
+ *   (sum_{j in line} F_j F_j^T + lambda I) x = rhs_x,
+ *
+ * run `iters` CG steps from the start value in X (overwritten with the result).  Each
+ * step computes the query vectors of all lines at once with one pass over S's pattern
+ * (S's values are ignored: the pass is the FusedMM of the pattern, M p = sum_j <p, F_j> F_j
+ * + lambda p), followed by one fused kernel that forms the step sizes per line and updates
+ * X, the residual and the direction.  A line with zero residual or curvature keeps its
+ * iterate.  rhs and X: nmajor x r float32; F: minor x r, dtype FMM_F32 or FMM_BF16;
+ * work: fmm_cg_work_size() bytes (three nmajor x r float32 blocks and nmajor scalars);
+ * ws: split partials of S as for the fused calls.  lambda >= 0.
+ */
+fmm_status fmm_cg_work_size(int32_t nmajor, int32_t r, size_t *bytes);
+fmm_status fmm_cg_lines(const fmm_sparse *S, const void *F, int32_t r, int32_t dtype, const float *rhs,
+                        float lambda, int32_t iters, float *X, float *work, size_t work_bytes, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Squared Frobenius residual of the factorisation on the observed entries (the ALS loss
+ * of Section VI-E): *out = sum_p (val[p] - <A_i, B_j>)^2 over S's stored entries
+ * (val = observed values; NULL means all ones), with the prediction an SDDMM on S's
+ * pattern.  out is one device float64; the sum is accumulated in float64 in a fixed
+ * order.  ws: fmm_residual_workspace() bytes.
+ */
+fmm_status fmm_residual_workspace(const fmm_sparse *S, size_t *bytes);
+fmm_status fmm_sddmm_residual(const fmm_sparse *S_csr, const void *A, const void *B, int32_t r, int32_t dtype,
+                              double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batched graphs */
 
 /*

@@ -7,6 +7,9 @@ from ._capi import FmmError, load as _load_library  # noqa: F401
 from .fusedmm import (  # noqa: F401
     BatchPlan,
     Pattern,
+    als_residual,
+    als_sweep,
+    cg_lines,
     device_info,
     dtype_code,
     fusedmm_a,

@@ -226,6 +226,29 @@ fmm_status check_ws2(const fmm_sparse *a, const fmm_sparse *b, int32_t r, size_t
 
 }  // namespace
 
+// ---------------------------------------------------------------- internal helpers
+
+namespace fmm {
+// out_line = sum over the line's stored entries of <H_line, G_j> G_j, with S's values
+// ignored (the pattern alone): the matrix-free product of the per-line Gram operator
+// used by batched conjugate gradients.  H and out are float32; G has storage dtype.
+fmm_status gram_apply(const fmm_sparse *S, const float *H, const void *G, int32_t r, int32_t dtype, float *out,
+                      void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    if (k.path == PATH_F64) return FMM_ERR_DTYPE;
+    FMM_TRY(check_ws(S, r, k.obytes, ws, ws_bytes));
+    LineArgs a = base_args(S, r, ws);
+    a.val = nullptr;
+    a.H = H;
+    a.G1 = G;
+    a.out = out;
+    FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S, st));
+    return FMM_OK;
+}
+}  // namespace fmm
+
 extern "C" {
 
 int32_t fmm_abi_version(void) { return FMM_ABI_VERSION; }

@@ -40,6 +40,11 @@ template <int OP, class TH, class TG1, class TG2, class Acc>
 hipError_t launch_lines(const LineArgs &a, int32_t n_splits, const int32_t *splits, Shape hint,
                         hipStream_t stream);
 
+// Gram operator of each major line of S on the pattern alone (api.hip):
+// out_line = sum_j <H_line, G_j> G_j.
+fmm_status gram_apply(const fmm_sparse *S, const float *H, const void *G, int32_t r, int32_t dtype, float *out,
+                      void *ws, size_t ws_bytes, hipStream_t st);
+
 // Pattern preparation kernels (pattern.hip).
 size_t scan_workspace_bytes(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s);

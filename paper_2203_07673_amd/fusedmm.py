@@ -24,7 +24,8 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward"]
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "cg_lines", "als_residual",
+           "als_sweep"]
 
 DEFAULT_LONG_LEN = 256
 DEFAULT_CHUNK = 256
@@ -499,6 +500,57 @@ def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=Non
     C.call("fmm_gat_forward", ctypes.byref(P.csr), _ptr(s), _ptr(t), _ptr(H), r, dcode, float(negative_slope),
            C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(ws), nb.value, _stream())
     return out
+
+
+def cg_lines(P: Pattern, orient, F, rhs, lam, iters, X):
+    """Batched CG on (sum_{j in line} F_j F_j^T + lam I) x = rhs for every line of the
+    given orientation of P (rows for FMM_CSR, columns for FMM_CSC); X is updated in place."""
+    desc = P.descriptor(orient)
+    nmaj = P.m if orient == C.FMM_CSR else P.n
+    r = F.shape[1]
+    dcode = dtype_code(F)
+    _check_dense("X", X, nmaj, r, P.device)
+    _check_dense("rhs", rhs, nmaj, r, P.device)
+    if X.dtype != torch.float32 or rhs.dtype != torch.float32:
+        raise TypeError("X and rhs are float32")
+    wb = ctypes.c_size_t(0)
+    C.call("fmm_cg_work_size", nmaj, r, ctypes.byref(wb))
+    work = P._ws_cache.get(("cg", wb.value))
+    if work is None:
+        work = torch.empty(wb.value // 4, dtype=torch.float32, device=P.device)
+        P._ws_cache[("cg", wb.value)] = work
+    ws, wsb = P.workspace(C.FMM_OP_FUSEDMM_A if orient == C.FMM_CSR else C.FMM_OP_FUSEDMM_B, r, dcode)
+    C.call("fmm_cg_lines", ctypes.byref(desc), _ptr(F), r, dcode, _ptr(rhs), float(lam), int(iters), _ptr(X),
+           _ptr(work), wb.value, _ptr(ws), wsb, _stream())
+    return X
+
+
+def als_residual(P: Pattern, A, B):
+    """sum over observed entries of (C~_ij - <A_i, B_j>)^2 (P's values are the observations),
+    as a float64 device scalar."""
+    r = A.shape[1]
+    dcode = dtype_code(A)
+    nb = ctypes.c_size_t(0)
+    C.call("fmm_residual_workspace", ctypes.byref(P.csr), ctypes.byref(nb))
+    ws = P._ws_cache.get(("res", nb.value))
+    if ws is None:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
+        P._ws_cache[("res", nb.value)] = ws
+    out = torch.empty((), dtype=torch.float64, device=P.device)
+    C.call("fmm_sddmm_residual", ctypes.byref(P.csr), _ptr(A), _ptr(B), r, dcode, _ptr(out), _ptr(ws), nb.value,
+           _stream())
+    return out
+
+
+def als_sweep(P: Pattern, A, B, lam, cg_iters):
+    """One alternating-least-squares sweep on the observed values stored in P: solve for A
+    with B fixed, then for B with A fixed, each by `cg_iters` batched CG steps (the paper's
+    ALS application: the CG query vectors of all rows come from one FusedMM-shaped pass)."""
+    rhs_a = spmm_a_raw(P, B)  # sum_j C~_ij B_j
+    cg_lines(P, C.FMM_CSR, B, rhs_a, lam, cg_iters, A)
+    rhs_b = spmm_b_raw(P, A)  # sum_i C~_ij A_i
+    cg_lines(P, C.FMM_CSC, A, rhs_b, lam, cg_iters, B)
+    return A, B
 
 
 def to_bf16(x: torch.Tensor) -> torch.Tensor:

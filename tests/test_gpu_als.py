@@ -1,0 +1,72 @@
+"""GPU parity of batched CG and the ALS residual (Section VI-E) against the oracle.
+
+CG is an iteration: the GPU (float32) and the oracle (float64) follow the same
+recurrence, and on a well-conditioned system (lambda = 1, F ~ N(0, 1/r), so each
+line's matrix has eigenvalues of order 1-3) their iterates stay within a few
+units of float32 rounding times the condition number and the step count; the
+gate below (1e-4 of the iterate's size per line) leaves a wide margin for that.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_07673_amd as F
+from paper_2203_07673_amd import _capi as C
+from tests.gpu_helpers import dev, host, log
+from workloads import CsrPattern, dense_normal, er_exact_degree, rmat
+
+pytestmark = pytest.mark.gpu
+
+
+def _rowrel(got, ref):
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-30)
+    return float(np.max(np.abs(got - ref).max(axis=1) / np.maximum(den, 1e-3 * np.abs(ref).max())))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("iters", [1, 5, 10])
+def test_cg_lines_parity(dtype, iters):
+    S = rmat(11, 8, seed=520)
+    r, lam = 32, 1.0
+    Fa = dense_normal(S.n, r, 521, sigma=r ** -0.5)
+    Fb = dense_normal(S.m, r, 522, sigma=r ** -0.5)
+    rhs_a = dense_normal(S.m, r, 523)
+    rhs_b = dense_normal(S.n, r, 524)
+    X0a = dense_normal(S.m, r, 525)
+    X0b = dense_normal(S.n, r, 526)
+    log(f"cg dtype={dtype} iters={iters}")
+    P = F.Pattern.from_csr(S, long_len=64, chunk=32)
+    ST = oracle.transpose(S)
+    for orient, Fm, rhs, X0, pat in ((C.FMM_CSR, Fa, rhs_a, X0a, S), (C.FMM_CSC, Fb, rhs_b, X0b, ST)):
+        Fd = F.to_bf16(dev(Fm)) if dtype == torch.bfloat16 else dev(Fm)
+        Fq = oracle.bf16_round(Fm) if dtype == torch.bfloat16 else Fm
+        X = dev(X0).clone()
+        F.cg_lines(P, orient, Fd, dev(rhs), lam, iters, X)
+        ref = oracle.cg_lines(pat, Fq, rhs, lam, iters, X0)
+        err = _rowrel(host(X), ref)
+        assert err <= 1e-4, (orient, err)
+
+
+def test_residual_and_als_sweeps_reduce_loss():
+    m = n = 4096
+    r = 16
+    S = er_exact_degree(m, n, 24, seed=530)
+    At, Bt = dense_normal(m, r, 531, sigma=r ** -0.5), dense_normal(n, r, 532, sigma=r ** -0.5)
+    rows = np.repeat(np.arange(m), 24)
+    obs = (np.einsum("ij,ij->i", At[rows], Bt[S.colidx]) +
+           0.01 * np.random.default_rng(533).standard_normal(S.nnz)).astype(np.float32)
+    Sobs = CsrPattern(m, n, S.rowptr, S.colidx, obs)
+    log("als sweeps")
+    P = F.Pattern.from_csr(Sobs)
+    A = dev(dense_normal(m, r, 534, sigma=0.1))
+    B = dev(dense_normal(n, r, 535, sigma=0.1))
+    loss0 = float(F.als_residual(P, A, B))
+    ref0 = oracle.als_residual(Sobs, host(A), host(B))
+    assert abs(loss0 - ref0) <= 1e-5 * ref0
+    losses = [loss0]
+    for _ in range(4):
+        F.als_sweep(P, A, B, 1e-3, 10)
+        losses.append(float(F.als_residual(P, A, B)))
+    assert all(b < a for a, b in zip(losses, losses[1:])), losses
+    assert losses[-1] < 0.05 * losses[0], losses
