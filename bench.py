@@ -324,6 +324,12 @@ def run_gat(args):
     t32 = timeit(lambda: step(Hs), args.steps, args.warmup)
     H16 = [F.to_bf16(x) for x in Hs]
     t16 = timeit(lambda: step(H16), args.steps, args.warmup)
+
+    def step_unfused(Hl):
+        for h in range(heads):
+            F.gat_forward_unfused(P, Hl[h], a[h][0], a[h][1], softmax=True, out=outs[h])
+
+    tu = timeit(lambda: step_unfused(Hs), args.steps, args.warmup)
     # gather model per head: each stored entry fetches its feature row and t_j; rows read H once
     # for the scores and write out once
     nnz, n = S.nnz, S.n
@@ -331,6 +337,7 @@ def run_gat(args):
     out = {"metric": "graph-attention forward (4 heads, softmax) ms", "workload": "gat_rmat20_r128_h4",
            "nnz": nnz, "n": n, "r": r, "heads": heads,
            "fused_f32_ms": round(t32 * 1e3, 4), "fused_bf16_ms": round(t16 * 1e3, 4),
+           "unfused_f32_ms": round(tu * 1e3, 4), "speedup_fused_f32_vs_unfused_f32": round(tu / t32, 3),
            "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3)}
     print(json.dumps(out), flush=True)
 

@@ -355,6 +355,13 @@ fmm_status fmm_gat_workspace(const fmm_sparse *S, int32_t r, int32_t dtype, size
 fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, const void *H, int32_t r, int32_t dtype,
                            double negative_slope, int32_t flags, void *out, void *ws, size_t ws_bytes,
                            hipStream_t stream);
+/*
+ * The edge values w_ij themselves, in CSR order (nnz values, float32; float64 for
+ * FMM_F64): the unfused form, for a separate SpMM (fmm_spmm_a with w) or inspection.
+ * The row softmax sums in a fixed order per row.  S's split schedule is not used.
+ */
+fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t, int32_t dtype,
+                               double negative_slope, int32_t flags, void *w, hipStream_t stream);
 
 /* ---------------------------------------------------------------- alternating least squares */
 

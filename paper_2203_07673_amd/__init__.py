@@ -18,7 +18,9 @@ from .fusedmm import (  # noqa: F401
     fusedmm_b,
     fusedmm_b_backward_raw,
     fusedmm_b_raw,
+    gat_edge_values,
     gat_forward,
+    gat_forward_unfused,
     gat_scores,
     sddmm,
     sddmm_raw,

@@ -123,6 +123,7 @@ SIGNATURES = {
     "fmm_gat_scores": [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P],
     "fmm_gat_workspace": [_SP, _I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_gat_forward": [_SP, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _SZ, _P],
+    "fmm_gat_edge_values": [_SP, _P, _P, _I32, _D, _I32, _P, _P],
     "fmm_cg_work_size": [_I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_cg_lines": [_SP, _P, _I32, _I32, _P, ctypes.c_float, _I32, _P, _P, _SZ, _P, _SZ, _P],
     "fmm_residual_workspace": [_SP, ctypes.POINTER(_SZ)],

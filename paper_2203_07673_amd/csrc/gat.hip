@@ -62,6 +62,46 @@ __global__ __launch_bounds__(kBlock) void gat_scores_kernel(const TH *__restrict
     }
 }
 
+// Edge values of every stored entry, in CSR order (the unfused form: written to memory
+// for a separate SpMM).  A group of L lanes owns a row; lanes take the row's entries in
+// turn.  Softmax: the row maximum and the sum of exponentials are reduced over the group
+// (a fixed tree), then every value is rescaled.
+template <class Acc, int L>
+__global__ __launch_bounds__(kBlock) void gat_edges_kernel(int32_t n, const int32_t *__restrict__ ptr,
+                                                           const int32_t *__restrict__ idx, const Acc *__restrict__ val,
+                                                           const Acc *__restrict__ s, const Acc *__restrict__ t,
+                                                           Acc slope, bool softmax, Acc *__restrict__ w)
+{
+    const int lane = threadIdx.x % L;
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    if (row >= n) return;
+    const int32_t b = ptr[row], e = ptr[row + 1];
+    const Acc si = s[row];
+    Acc mx = neg_inf<Acc>();
+    for (int32_t p = b + lane; p < e; p += L) {
+        const Acc x = (val ? val[p] : Acc(1)) * (si + t[idx[p]]);
+        const Acc v = x >= Acc(0) ? x : slope * x;
+        w[p] = v;
+        mx = v > mx ? v : mx;
+    }
+    if (!softmax) return;
+    // group maximum: max is exact, so any reduction order gives the same bits
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) {
+        const Acc y = __shfl_xor(mx, o, L);
+        mx = y > mx ? y : mx;
+    }
+    Acc sum = Acc(0);
+    for (int32_t p = b + lane; p < e; p += L) {
+        const Acc v = exp_acc<Acc>(w[p] - mx);
+        w[p] = v;
+        sum += v;
+    }
+    sum = group_sum<L>(sum);
+    const Acc inv = sum > Acc(0) ? Acc(1) / sum : Acc(0);
+    for (int32_t p = b + lane; p < e; p += L) w[p] *= inv;
+}
+
 struct GatArgs {
     int32_t nlines, r;
     const int32_t *ptr, *idx;
@@ -435,6 +475,33 @@ fmm_status fmm_gat_workspace(const fmm_sparse *S, int32_t r, int32_t dtype, size
     const size_t ob = dtype == FMM_F64 ? 8 : 4;
     *bytes = S->n_chunks > 0 ? (size_t)S->n_chunks * ((size_t)r + 2) * ob : 0;
     return FMM_OK;
+}
+
+fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t, int32_t dtype, double negative_slope,
+                               int32_t flags, void *w, hipStream_t stream)
+{
+    if (!S) return FMM_ERR_NULL;
+    if (S->orient != FMM_CSR) return FMM_ERR_ORIENT;
+    if (S->rows < 0 || S->rows != S->cols || S->nnz < 0) return FMM_ERR_DIM;
+    if (!S->ptr || (S->nnz > 0 && (!S->idx || !w))) return FMM_ERR_NULL;
+    if (S->rows > 0 && (!s || !t)) return FMM_ERR_NULL;
+    if (flags & ~FMM_GAT_SOFTMAX) return FMM_ERR_DIM;
+    const bool softmax = (flags & FMM_GAT_SOFTMAX) != 0;
+    constexpr int L = 16;
+    const unsigned nb = (unsigned)(((int64_t)S->rows + kBlock / L - 1) / (kBlock / L));
+    if (nb == 0) return FMM_OK;
+    if (dtype == FMM_F64)
+        hipLaunchKernelGGL((gat_edges_kernel<double, L>), dim3(nb), dim3(kBlock), 0, stream, S->rows, S->ptr, S->idx,
+                           (const double *)S->val, (const double *)s, (const double *)t, negative_slope, softmax,
+                           (double *)w);
+    else if (dtype == FMM_F32 || dtype == FMM_BF16)
+        hipLaunchKernelGGL((gat_edges_kernel<float, L>), dim3(nb), dim3(kBlock), 0, stream, S->rows, S->ptr, S->idx,
+                           (const float *)S->val, (const float *)s, (const float *)t, (float)negative_slope, softmax,
+                           (float *)w);
+    else
+        return FMM_ERR_DTYPE;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMM_OK : hipfail(e);
 }
 
 }  // extern "C"

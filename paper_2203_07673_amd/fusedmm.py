@@ -24,7 +24,7 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "cg_lines", "als_residual",
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "cg_lines", "als_residual",
            "als_sweep"]
 
 DEFAULT_LONG_LEN = 256
@@ -551,6 +551,22 @@ def als_sweep(P: Pattern, A, B, lam, cg_iters):
     rhs_b = spmm_b_raw(P, A)  # sum_i C~_ij A_i
     cg_lines(P, C.FMM_CSC, A, rhs_b, lam, cg_iters, B)
     return A, B
+
+
+def gat_edge_values(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True):
+    """The attention edge values w (CSR order) that gat_forward applies without storing."""
+    dcode, odt = _common(P, H, None)
+    s, t = gat_scores(H, a1, a2)
+    w = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    C.call("fmm_gat_edge_values", ctypes.byref(P.csr), _ptr(s), _ptr(t), dcode, float(negative_slope),
+           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(w), _stream())
+    return w[:P.nnz]
+
+
+def gat_forward_unfused(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=None):
+    """The unfused attention head: edge values written to memory, then an SpMM reads them."""
+    w = gat_edge_values(P, H, a1, a2, negative_slope, softmax)
+    return spmm_a_raw(P, H, w=w, out=out)
 
 
 def to_bf16(x: torch.Tensor) -> torch.Tensor:

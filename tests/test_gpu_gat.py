@@ -121,3 +121,27 @@ def test_gat_rmat20_r128_sampled():
         Hq = oracle.bf16_round(H) if dtype == torch.bfloat16 else H
         ref, mag = _ref(S, Hq, a1, a2, 0.2, True, rows=rows)
         gate(f"rmat20 gat {dtype}", host(out[torch.from_numpy(rows).cuda()]), ref, mag, TOL_F32)
+
+
+@pytest.mark.parametrize("softmax", [True, False])
+def test_gat_edge_values_and_unfused_head(softmax):
+    S = rmat(11, 8, seed=440)
+    r = 64
+    H = dense_normal(S.n, r, 441)
+    a1 = dense_normal(1, r, 442, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 443, sigma=r ** -0.5)[0]
+    log(f"gat edge values softmax={softmax}")
+    P = F.Pattern.from_csr(S, long_len=64, chunk=32)
+    w = host(F.gat_edge_values(P, dev(H), dev(a1), dev(a2), softmax=softmax))
+    s, t = oracle.gat_scores(H, a1, a2)
+    ew = oracle.gat_edges(S, s, t, 0.2, softmax)
+    if softmax:
+        mag = np.abs(ew)
+    else:
+        ms, mt = oracle.gat_scores(np.abs(H), np.abs(a1), np.abs(a2))
+        rowsof = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+        mag = np.abs(S.val.astype(np.float64)) * (ms[rowsof] + mt[S.colidx])
+    gate(f"edge values softmax={softmax}", w, ew, mag, TOL_F32)
+    out = host(F.gat_forward_unfused(P, dev(H), dev(a1), dev(a2), softmax=softmax))
+    ref, mg = _ref(S, H, a1, a2, 0.2, softmax)
+    gate(f"unfused head softmax={softmax}", out, ref, mg, TOL_F32)
