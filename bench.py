@@ -160,6 +160,83 @@ def pmc_summary(fetch_dir, write_dir, out_json, command=""):
     print(json.dumps(out, indent=1))
 
 
+ROLES = {0: "SDDMM", 1: "SpMM, one operand", 2: "SpMM, two operands (dB = dP^T A + R^T dC)",
+         3: "fused one-row (FusedMMA forward / adjoint row pass)", 4: "fused two-row (adjoint column pass)"}
+
+
+def _role(key):
+    if key.startswith("line_kernel<"):
+        return ROLES.get(int(key[len("line_kernel<"):].split(",", 1)[0]), "line kernel")
+    if "merge_kernel" in key:
+        return "split-line merge"
+    if "f32_to_bf16" in key:
+        return "bf16 rounding of A, B"
+    return None
+
+
+def _pmc_per_key(d, counter):
+    per = {}
+    for row in _csv_rows(d, "counter_collection.csv"):
+        if row.get("Counter_Name") == counter:
+            per[int(row["Dispatch_Id"])] = (_short_kernel(row["Kernel_Name"]), float(row["Counter_Value"]))
+    return per
+
+
+def counter_table(out_md, runs, command=""):
+    """Counter-measured HBM traffic and rate of the hot-path kernels of several profiled
+    step variants.  Each run is NAME=TRACE_DIR:FETCH_DIR:WRITE_DIR, three rocprofv3 runs
+    of the same --profile-step command (kernel trace, FETCH_SIZE, WRITE_SIZE).  Counter
+    KiB are scaled by what the same counters read for the plain device copy of COPY_BYTES
+    that --calibrate-copy runs in that command."""
+    want_kib = COPY_BYTES / 1024.0
+    lines = ["# Counter-measured HBM traffic: fused vs unfused steps", "",
+             f"Command: `{command}`", "",
+             f"Peak: {HBM_PEAK_GBS:.0f} GB/s (MI355X HBM3E). Bytes per launch = FETCH_SIZE x scale_f + "
+             "WRITE_SIZE x scale_w (KiB x 1024); the scales make a plain 1 GiB device copy read and write "
+             "1 GiB. Rate = bytes per launch / average kernel-trace duration.", ""]
+    for spec in runs:
+        name, dirs = spec.split("=", 1)
+        trace_dir, fetch_dir, write_dir = dirs.split(":")
+        fetch, write = _pmc_per_key(fetch_dir, "FETCH_SIZE"), _pmc_per_key(write_dir, "WRITE_SIZE")
+        calib = [i for i, (k, v) in write.items() if "copy" in k.lower() and abs(v - want_kib) < 0.01 * want_kib
+                 and i in fetch]
+        if not calib:
+            raise SystemExit(f"{name}: no calibration copy found")
+        sf = want_kib / (sum(fetch[i][1] for i in calib) / len(calib))
+        sw = want_kib / (sum(write[i][1] for i in calib) / len(calib))
+        byk = {}
+        for i, (k, v) in fetch.items():
+            if i in calib or i not in write:
+                continue
+            b = (v * sf + write[i][1] * sw) * 1024.0
+            byk.setdefault(k, []).append(b)
+        stats = {_short_kernel(r["Name"]): r for r in _csv_rows(trace_dir, "kernel_stats.csv")}
+        lines += [f"## {name}", "", f"Scales: FETCH x {sf:.4f}, WRITE x {sw:.4f}.", "",
+                  "| kernel | role | calls | avg us | counter MB / launch | counter GB/s | % of peak |",
+                  "|---|---|---|---|---|---|---|"]
+        tot_b = tot_t = 0.0
+        for k in sorted(byk, key=lambda k: -float(stats.get(k, {}).get("TotalDurationNs", 0))):
+            role = _role(k)
+            if role is None or k not in stats:
+                continue
+            calls = int(stats[k]["Calls"])
+            avg_ns = float(stats[k]["AverageNs"])
+            b = sum(byk[k]) / len(byk[k])
+            gbs = b / avg_ns
+            lines.append(f"| `{k}` | {role} | {calls} | {avg_ns / 1e3:.1f} | {b / 1e6:.1f} | {gbs:.0f} | "
+                         f"{100 * gbs / HBM_PEAK_GBS:.1f} |")
+            if role != "bf16 rounding of A, B":
+                tot_b += b * calls
+                tot_t += avg_ns * calls
+        if tot_t > 0:
+            lines.append(f"| **all hot-path launches** | | | {tot_t / 1e3:.1f} (sum) | {tot_b / 1e6:.1f} (sum) | "
+                         f"**{tot_b / tot_t:.0f}** | **{100 * tot_b / tot_t / HBM_PEAK_GBS:.1f}** |")
+        lines.append("")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def trace_summary(trace_dir, out_md, command=""):
     rows = _csv_rows(trace_dir, "kernel_stats.csv")
     lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
@@ -386,6 +463,38 @@ def run_als(args):
     print(json.dumps(out), flush=True)
 
 
+def calibrate_copy(dev):
+    """Three plain device copies of COPY_BYTES: the reference dispatches for scaling counters."""
+    import torch
+
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
+    """One step variant alone, for kernel traces and counter runs of that variant."""
+    import torch
+
+    dev = A.device
+    if args.profile_step == "fused_f32":
+        step = make_step(A, B, fused=True)
+    elif args.profile_step == "unfused_f32":
+        R_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        dP_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        step = make_step(A, B, fused=False, R_ws=R_ws, dP_ws=dP_ws)
+    else:
+        step = make_step(F.to_bf16(A), F.to_bf16(B), fused=True)
+    t, kt = time_steps(step, args.steps, args.warmup)
+    if args.calibrate_copy:
+        calibrate_copy(dev)
+    print(json.dumps({"profile_step": args.profile_step, "workload": args.workload, "ms_per_step": round(t * 1e3, 4),
+                      "gflops": round(flops / t / 1e9, 1), "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +509,10 @@ def main():
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--counter-table", nargs="+", metavar="OUT_MD NAME=TRACE:FETCH:WRITE",
+                    help="markdown table of counter-measured traffic per hot-path kernel and step variant")
+    ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16"),
+                    help="run only this step variant (default batch-depth heuristic, no autotune), for profiling")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -407,6 +520,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(*args.trace_summary, command=args.command)
+        return
+    if args.counter_table:
+        counter_table(args.counter_table[0], args.counter_table[1:], command=args.command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -483,6 +599,9 @@ def main():
         return t, ktimes
 
     flops = 12.0 * r * nnz
+    if args.profile_step:
+        profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz)
+        return
     tuned = P.autotune(A, B, G, form="a")
     log(f"autotuned batch variants (f32): {tuned}")
     step_f32 = make_step(A, B, fused=True)
@@ -553,12 +672,7 @@ def main():
         variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)
 
     if args.calibrate_copy:
-        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy(dev)
 
     out = {
         "metric": METRIC,

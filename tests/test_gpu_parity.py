@@ -424,3 +424,25 @@ def test_batch_variants_parity(dtype):
     gate("autotuned FusedMMA", host(Cg), ref, mag, tol)
     got = P.autotune(Ad, Bd, dev(Gb, odt), form="b")
     assert got["csr"] in (1, 2, 3) and got["csc"] in (1, 2, 3)
+
+
+@pytest.mark.parametrize("m,n", [(5, 4), (0, 3), (3, 0), (0, 0)])
+def test_patterns_without_entries(m, n):
+    """nnz = 0 (and zero-size sides): every output is exactly zero, SDDMM is empty,
+    and the adjoint calls run, for fused and unfused forms."""
+    r = 8
+    S = CsrPattern(m, n, np.zeros(m + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    A, B = _inputs(S, r, 191, torch.float32)
+    log(f"no entries m={m} n={n}")
+    P = _pattern(S)
+    assert P.colptr.cpu().numpy().tolist() == [0] * (n + 1)
+    Ad, Bd = dev(A), dev(B)
+    for fused in (True, False):
+        Ca, R = F.fusedmm_a_raw(P, Ad, Bd, fused=fused)
+        Cb, _ = F.fusedmm_b_raw(P, Ad, Bd, fused=fused)
+        assert tuple(Ca.shape) == (m, r) and tuple(Cb.shape) == (n, r)
+        assert not host(Ca).any() and not host(Cb).any()
+        gA, gB = F.fusedmm_a_backward_raw(P, Ad, Bd, dev(dense_normal(m, r, 192)), fused=fused, R_ws=R)
+        assert not host(gA).any() and not host(gB).any()
+    assert F.sddmm_raw(P, Ad, Bd).numel() == 0
+    assert not host(F.spmm_a_raw(P, Bd)).any() and not host(F.spmm_b_raw(P, Ad)).any()
