@@ -23,6 +23,7 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+NO_SPLIT = 1 << 30  # a split threshold no line reaches
 METRIC = "FusedMM fwd+bwd GFLOP/s and % HBM peak; fused/BF16 vs unfused FP32 at tol"
 
 
@@ -463,6 +464,14 @@ def run_als(args):
     print(json.dumps(out), flush=True)
 
 
+def restore_tuning(P, variants, splits):
+    """Put back an autotuned batch depth and split threshold per orientation."""
+    from paper_2203_07673_amd import _capi as CA
+    for o, k in ((CA.FMM_CSR, "csr"), (CA.FMM_CSC, "csc")):
+        P.set_split(o, splits[k] if splits[k] is not None else NO_SPLIT)
+    P.set_variant(variants["csr"], variants["csc"])
+
+
 def calibrate_copy(dev):
     """Three plain device copies of COPY_BYTES: the reference dispatches for scaling counters."""
     import torch
@@ -479,6 +488,12 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
     import torch
 
     dev = A.device
+    if args.tuned:
+        from paper_2203_07673_amd import _capi as CA
+        vr, vc, lr, lc = (int(x) for x in args.tuned.split(","))
+        for o, ll in ((CA.FMM_CSR, lr), (CA.FMM_CSC, lc)):
+            P.set_split(o, ll if ll > 0 else NO_SPLIT)
+        P.set_variant(vr, vc)
     if args.profile_step == "fused_f32":
         step = make_step(A, B, fused=True)
     elif args.profile_step == "unfused_f32":
@@ -490,7 +505,8 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
     t, kt = time_steps(step, args.steps, args.warmup)
     if args.calibrate_copy:
         calibrate_copy(dev)
-    print(json.dumps({"profile_step": args.profile_step, "workload": args.workload, "ms_per_step": round(t * 1e3, 4),
+    print(json.dumps({"profile_step": args.profile_step, "workload": args.workload, "variants": P.variants,
+                      "splits": P.splits, "ms_per_step": round(t * 1e3, 4),
                       "gflops": round(flops / t / 1e9, 1), "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}),
           flush=True)
 
@@ -512,7 +528,11 @@ def main():
     ap.add_argument("--counter-table", nargs="+", metavar="OUT_MD NAME=TRACE:FETCH:WRITE",
                     help="markdown table of counter-measured traffic per hot-path kernel and step variant")
     ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16"),
-                    help="run only this step variant (default batch-depth heuristic, no autotune), for profiling")
+                    help="run only this step variant, for profiling (no autotune: the batch depth and split "
+                         "threshold come from --tuned, else the defaults)")
+    ap.add_argument("--tuned", default="",
+                    help="CSR_VARIANT,CSC_VARIANT,CSR_LONG_LEN,CSC_LONG_LEN as a bench run's autotune chose them "
+                         "(long_len 0 = no split schedule)")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -603,7 +623,8 @@ def main():
         profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz)
         return
     tuned = P.autotune(A, B, G, form="a")
-    log(f"autotuned batch variants (f32): {tuned}")
+    splits = P.splits
+    log(f"autotuned batch variants (f32): {tuned}, split thresholds {splits}")
     step_f32 = make_step(A, B, fused=True)
     log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
     t_step, kt = time_steps(step_f32, args.steps, args.warmup)
@@ -643,11 +664,13 @@ def main():
         log(f"unfused f32 step {t_unf * 1e3:.3f} ms")
         del R_ws, dP_ws
         A16, B16 = F.to_bf16(A), F.to_bf16(B)
+        keep = (dict(tuned), dict(splits))
         tuned16 = P.autotune(A16, B16, G, form="a")
         t_bf, kt_bf = time_steps(make_step(A16, B16, fused=True), vsteps, 2)
         variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
                                   "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()},
-                                  "batch_variants": tuned16}
+                                  "batch_variants": tuned16, "split_long_len": P.splits}
+        restore_tuning(P, *keep)
         log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
         variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
         variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
@@ -688,7 +711,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "r": r, "storage": "f32",
-                   "batch_variants": tuned,
+                   "batch_variants": tuned, "split_long_len": splits,
                    "step": "fused FusedMMA forward + adjoint (dA row pass, dB column pass)",
                    "flops_per_step": flops},
         "roofline": roofline,

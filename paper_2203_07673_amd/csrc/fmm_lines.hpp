@@ -383,21 +383,13 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     const int32_t ps = wperm ? 1 : 0;
     const bool partial = C < L * NV;  // some lanes own no vector of r (uniform)
 
-    // One batch of U entries from p0.  FULL: all U entries lie in the line.  Otherwise the
-    // entries past `end` read the last entry's index (one unconditional load) but load no
-    // row, and are left out of every sum and store.  Their row registers are left as they
-    // are, not zeroed: a zero write to a register that an in-flight load targets would
-    // force a wait for that load, serialising the batch.
-    auto run_batch = [&](int32_t p0, auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        int32_t j[U];
-        bool okv[U];
-        Acc w1[U], w2[U];
+    // Per-entry operands of one batch (column indices and weights).  Entries past `end`
+    // read the last entry of the line, so every load is unconditional and in bounds.
+    auto load_meta = [&](int32_t p0, int32_t *j, Acc *w1, Acc *w2) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
-            okv[u] = FULL || p < end;
-            const int32_t pc = okv[u] ? p : end - 1;
+            const int32_t pc = p < end ? p : end - 1;
             j[u] = idx[pc];
             const Acc base = val_p[pc * vs];
             if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
@@ -409,6 +401,21 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 w2[u] = Acc(0);
             }
         }
+    };
+
+    // One batch of U entries from p0 whose operands (j, w1, w2) are already loaded.
+    // FULL: all U entries lie in the line.  Otherwise the entries past `end` load no row
+    // and are left out of every sum and store.  Their row registers are left as they are,
+    // not zeroed: a zero write to a register that an in-flight load targets would force a
+    // wait for that load, serialising the batch.  After the row loads are issued, the
+    // operands of the batch at `pn` are loaded into (jn, w1n, w2n), so that they arrive
+    // while this batch waits for its rows.
+    auto run_batch = [&](int32_t p0, auto full_tag, const int32_t *j, const Acc *w1, const Acc *w2, int32_t pn,
+                         int32_t *jn, Acc *w1n, Acc *w2n) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        bool okv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) okv[u] = FULL || p0 + u < end;
         Raw<TG1, VW> g1[U][NV];
         Raw<TG2, VW> g2[kTwo ? U : 1][kTwo ? NV : 1];
 #pragma unroll
@@ -424,6 +431,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 }
             }
         }
+        load_meta(pn, jn, w1n, w2n);  // past the line it rereads the last entry
         if (partial) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -528,9 +536,22 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         }
     };
 
-    for (int32_t p0 = begin + gidx * U; p0 < end; p0 += U * GPL) {
-        if (p0 + U <= end) run_batch(p0, std::true_type{});
-        else run_batch(p0, std::false_type{});
+    {
+        int32_t j[U], jn[U];
+        Acc w1[U], w2[U], w1n[U], w2n[U];
+        int32_t p0 = begin + gidx * U;
+        if (p0 < end) load_meta(p0, j, w1, w2);
+        for (; p0 < end; p0 += U * GPL) {
+            const int32_t pn = p0 + U * GPL;
+            if (p0 + U <= end) run_batch(p0, std::true_type{}, j, w1, w2, pn, jn, w1n, w2n);
+            else run_batch(p0, std::false_type{}, j, w1, w2, pn, jn, w1n, w2n);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                j[u] = jn[u];
+                w1[u] = w1n[u];
+                w2[u] = w2n[u];
+            }
+        }
     }
 
     if constexpr (OP != OP_SDDMM) {
@@ -617,8 +638,18 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(const int32_t *__restrict
     const int32_t s = (int32_t)(t / r);
     const int32_t k = (int32_t)(t % r);
     const int32_t line = splits[3 * s], first = splits[3 * s + 1], cnt = splits[3 * s + 2];
+    const Acc *p = partial + (size_t)first * r + k;
     Acc sum = Acc(0);
-    for (int32_t c = 0; c < cnt; ++c) sum += partial[(size_t)(first + c) * r + k];
+    int32_t c = 0;
+    // eight loads in flight, added in chunk order
+    for (; c + 8 <= cnt; c += 8) {
+        Acc v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + u) * r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; c < cnt; ++c) sum += p[(size_t)c * r];
     Acc *o = out + (size_t)line * r + k;
     *o = (beta == 0.0) ? sum : Acc(beta) * *o + sum;
 }

@@ -252,18 +252,35 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 
 // ------------------------------------------------------------------ bfloat16 storage
 
-__global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float *__restrict__ x, uint16_t *__restrict__ y, int64_t n)
+__device__ inline uint32_t bf16_bits(float f)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7FC0u;  // canonical quiet NaN
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;                               // nearest, ties to even
+}
+
+// Elements [begin, n), one per thread.
+__global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float *__restrict__ x, uint16_t *__restrict__ y,
+                                                          int64_t begin, int64_t n)
+{
+    const int64_t i = begin + (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const uint32_t u = __float_as_uint(x[i]);
-    uint16_t o;
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-        o = 0x7FC0;  // canonical quiet NaN
-    } else {
-        o = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);  // nearest, ties to even
-    }
-    y[i] = o;
+    y[i] = (uint16_t)bf16_bits(x[i]);
+}
+
+// Groups of 8 elements (two 16-byte loads, one 16-byte store); x and y 16-byte aligned.
+__global__ __launch_bounds__(256) void f32_to_bf16_x8_kernel(const float4 *__restrict__ x, uint4 *__restrict__ y,
+                                                             int64_t groups)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= groups) return;
+    const float4 a = x[2 * g], b = x[2 * g + 1];
+    uint4 o;
+    o.x = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
+    o.y = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
+    o.z = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
+    o.w = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
+    y[g] = o;
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -436,7 +453,23 @@ hipError_t schedule_fill(const int32_t *ptr, int32_t nmajor, int32_t long_len, i
 hipError_t f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+    int64_t done = 0;
+    if ((uintptr_t)x % 16 == 0 && (uintptr_t)y % 16 == 0) {
+        const int64_t groups = n / 8;
+        if (groups > 0) {
+            const int64_t nb = (groups + 255) / 256;
+            if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            hipLaunchKernelGGL(f32_to_bf16_x8_kernel, dim3((unsigned)nb), dim3(256), 0, s,
+                               reinterpret_cast<const float4 *>(x), reinterpret_cast<uint4 *>(y), groups);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        done = groups * 8;
+    }
+    if (done == n) return hipSuccess;
+    const int64_t nb = (n - done + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, y, done, n);
     return hipGetLastError();
 }
 

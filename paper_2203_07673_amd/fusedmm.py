@@ -27,8 +27,9 @@ __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to
            "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "cg_lines", "als_residual",
            "als_sweep"]
 
-DEFAULT_LONG_LEN = 256
-DEFAULT_CHUNK = 256
+DEFAULT_LONG_LEN = 128
+DEFAULT_CHUNK = 128
+SPLIT_CANDIDATES = (256, 128, 64)
 
 
 def _stream():
@@ -101,6 +102,7 @@ class Pattern:
             raise ValueError("val must have nnz entries")
         self._csr_sched = None
         self._csc_sched = None
+        self._split = split
         self._ws_cache = {}
         if validate:
             C.call("fmm_validate", ctypes.byref(self._desc(C.FMM_CSR, with_sched=False)), _stream())
@@ -173,6 +175,24 @@ class Pattern:
             return self.csr if orient == C.FMM_CSR else self.csc
         return self._desc(orient, with_sched=False)
 
+    def set_split(self, orient, long_len, chunk=None):
+        """Rebuild one orientation's split schedule: lines longer than long_len are cut
+        into chunks of `chunk` (default long_len) entries.  The batch depth is kept."""
+        keep = self.csr.variant if orient == C.FMM_CSR else self.csc.variant
+        chunk = chunk or long_len
+        if orient == C.FMM_CSR:
+            self._csr_sched = self._schedule(self.rowptr, self.m, long_len, chunk)
+            self.csr = self._desc(C.FMM_CSR)
+            self.csr.variant = keep
+        else:
+            self._csc_sched = self._schedule(self.colptr, self.n, long_len, chunk)
+            self.csc = self._desc(C.FMM_CSC)
+            self.csc.variant = keep
+
+    def max_line(self, orient):
+        ptr = self.rowptr if orient == C.FMM_CSR else self.colptr
+        return int((ptr[1:] - ptr[:-1]).max().item()) if ptr.numel() > 1 else 0
+
     def set_variant(self, csr=None, csc=None):
         """Batch depth class of each orientation (FMM_VARIANT_*; 0 = automatic)."""
         if csr is not None:
@@ -192,9 +212,12 @@ class Pattern:
     def variants(self):
         return {"csr": self.csr.variant, "csc": self.csc.variant}
 
-    def autotune(self, A, B, dC, form="a"):
-        """Time the batch variants of FusedMMA (form "a") or FusedMMB ("b") forward and
-        adjoint on these operands and keep the fastest per orientation."""
+    def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES):
+        """Time FusedMMA (form "a") or FusedMMB ("b") forward and adjoint on these operands
+        and keep, per orientation, the fastest split threshold (from split_candidates,
+        where some line is longer) and batch depth.  The library's fmm_autotune picks the
+        depth for each threshold; the forward times the orientation the forward runs on,
+        the two-row adjoint pass the other one."""
         r = A.shape[1]
         dcode, odt = _common(self, A, B)
         rows_out = self.m if form == "a" else self.n
@@ -202,10 +225,65 @@ class Pattern:
         dA = torch.empty(self.m, r, dtype=odt, device=self.device)
         dB = torch.empty(self.n, r, dtype=odt, device=self.device)
         op = C.FMM_OP_FUSEDMM_A_BWD if form == "a" else C.FMM_OP_FUSEDMM_B_BWD
-        ws, wb = self.workspace(op, r, dcode)
-        C.call("fmm_autotune", op, ctypes.byref(self.csr), ctypes.byref(self.csc), _ptr(A), _ptr(B), _ptr(dC), r,
-               dcode, _ptr(C_out), _ptr(dA), _ptr(dB), _ptr(ws), wb, _stream())
+        own, other = (C.FMM_CSR, C.FMM_CSC) if form == "a" else (C.FMM_CSC, C.FMM_CSR)
+        if form == "a":
+            def fwd():
+                fusedmm_a_raw(self, A, B, out=C_out)
+
+            def two_row():
+                fusedmm_a_backward_raw(self, A, B, dC, dB=dB, need=(False, True))
+        else:
+            def fwd():
+                fusedmm_b_raw(self, A, B, out=C_out)
+
+            def two_row():
+                fusedmm_b_backward_raw(self, A, B, dC, dA=dA, need=(True, False))
+
+        def time_it(fn, reps=3):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        def tune_depth():
+            ws, wb = self.workspace(op, r, dcode)
+            C.call("fmm_autotune", op, ctypes.byref(self.csr), ctypes.byref(self.csc), _ptr(A), _ptr(B), _ptr(dC),
+                   r, dcode, _ptr(C_out), _ptr(dA), _ptr(dB), _ptr(ws), wb, _stream())
+
+        longest = max(self.max_line(C.FMM_CSR), self.max_line(C.FMM_CSC))
+        cands = [ll for ll in split_candidates if ll < longest] if self._split else []
+        if len(cands) <= 1:
+            if cands:
+                for o in (C.FMM_CSR, C.FMM_CSC):
+                    self.set_split(o, cands[0])
+            tune_depth()
+            return self.variants
+        best = {}
+        for ll in cands:
+            for o in (C.FMM_CSR, C.FMM_CSC):
+                self.set_split(o, ll)
+            tune_depth()
+            for o, fn in ((own, fwd), (other, two_row)):
+                ms = time_it(fn)
+                v = self.csr.variant if o == C.FMM_CSR else self.csc.variant
+                if o not in best or ms < best[o][0]:
+                    best[o] = (ms, ll, v)
+        for o, (_, ll, v) in best.items():
+            self.set_split(o, ll)
+            if o == C.FMM_CSR:
+                self.csr.variant = v
+            else:
+                self.csc.variant = v
         return self.variants
+
+    @property
+    def splits(self):
+        """Split threshold (long_len) of each orientation's schedule, None without one."""
+        return {k: (s["long_len"] if s is not None else None) for k, s in self.schedules.items()}
 
     @property
     def schedules(self):

@@ -147,6 +147,11 @@ def test_bf16_rounding_matches_oracle():
     assert np.array_equal(y, ref)
     ynan = F.to_bf16(dev(np.array([np.nan], np.float32))).float().cpu().numpy()
     assert np.isnan(ynan[0])
+    # 8-wide groups plus a ragged tail, and a source that is not 16-byte aligned (one-per-thread path)
+    xd = dev(x)
+    for lo, hi in ((0, 13), (0, 100003), (1, 100004), (3, 11)):
+        y = F.to_bf16(xd[lo:hi]).view(torch.int16).cpu().numpy().view(np.uint16)
+        assert np.array_equal(y, ref[lo:hi]), (lo, hi)
 
 
 FWD_SHAPES = [
