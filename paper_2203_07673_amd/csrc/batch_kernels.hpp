@@ -54,11 +54,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__re
                 const int32_t b = g.rowptr[line], e = g.rowptr[line + 1];
                 if (tl.pass == PASS_FWD) {
                     o.H = g.A;
-                    process_line<OP_FUSED1, TS, TS, TS, float, L, 1, VW, UR, GPL_R>(
+                    process_line<OP_FUSED1, TS, TS, TS, float, L, 1, VW, UR, GPL_R, false>(
                         o, lane, gidx, line, b, e, g.C + (size_t)line * r, false);
                 } else {
                     o.H = g.dC;
-                    process_line<OP_FUSED1, float, TS, TS, float, L, 1, VW, UR, GPL_R>(
+                    process_line<OP_FUSED1, float, TS, TS, float, L, 1, VW, UR, GPL_R, false>(
                         o, lane, gidx, line, b, e, g.dA + (size_t)line * r, false);
                 }
             }
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__re
             o.G2 = g.dC;
             for (int32_t line = tl.l0 + slot; line < tl.l1; line += LPB) {
                 const int32_t b = g.colptr[line], e = g.colptr[line + 1];
-                process_line<OP_FUSED2, TS, TS, float, float, L, 1, VW, UC, GPL_C>(
+                process_line<OP_FUSED2, TS, TS, float, float, L, 1, VW, UC, GPL_C, false>(
                     o, lane, gidx, line, b, e, g.dB + (size_t)line * r, false);
             }
         }

@@ -323,7 +323,7 @@ struct LineOperands {
 // line (GPL > 1: wavefront-per-line; group gidx takes every GPL-th batch of U entries
 // and the partial sums are added across groups at the end).  dst receives the line's
 // r-vector (beta applied when keep_beta); OP_SDDMM writes per-entry values instead.
-template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U, int GPL>
+template <int OP, class TH, class TG1, class TG2, class Acc, int L, int NV, int VW, int U, int GPL, bool PF = true>
 __device__ __forceinline__ void process_line(const LineOperands &o, int lane, int gidx, int32_t line, int32_t begin,
                                              int32_t end, Acc *dst, bool keep_beta)
 {
@@ -384,12 +384,13 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     const bool partial = C < L * NV;  // some lanes own no vector of r (uniform)
 
     // Per-entry operands of one batch (column indices and weights).  Entries past `end`
-    // read the last entry of the line, so every load is unconditional and in bounds.
-    auto load_meta = [&](int32_t p0, int32_t *j, Acc *w1, Acc *w2) {
+    // read the last entry of the line, so every load is in bounds.
+    auto load_meta = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2) {
+        constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
-            const int32_t pc = p < end ? p : end - 1;
+            const int32_t pc = (FULL || p < end) ? p : end - 1;
             j[u] = idx[pc];
             const Acc base = val_p[pc * vs];
             if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
@@ -403,16 +404,18 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         }
     };
 
-    // One batch of U entries from p0 whose operands (j, w1, w2) are already loaded.
-    // FULL: all U entries lie in the line.  Otherwise the entries past `end` load no row
+    // One batch of U entries from p0 with operands (j, w1, w2): already loaded with PF,
+    // else loaded here first.  FULL: all U entries lie in the line.  Otherwise the entries past `end` load no row
     // and are left out of every sum and store.  Their row registers are left as they are,
     // not zeroed: a zero write to a register that an in-flight load targets would force a
     // wait for that load, serialising the batch.  After the row loads are issued, the
     // operands of the batch at `pn` are loaded into (jn, w1n, w2n), so that they arrive
-    // while this batch waits for its rows.
-    auto run_batch = [&](int32_t p0, auto full_tag, const int32_t *j, const Acc *w1, const Acc *w2, int32_t pn,
-                         int32_t *jn, Acc *w1n, Acc *w2n) {
+    // while this batch waits for its rows (PF; the batched persistent kernel, whose rows
+    // are mostly L2 hits, runs faster without it).
+    auto run_batch = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2, int32_t pn, int32_t *jn,
+                         Acc *w1n, Acc *w2n) {
         constexpr bool FULL = decltype(full_tag)::value;
+        if constexpr (!PF) load_meta(p0, full_tag, j, w1, w2);
         bool okv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) okv[u] = FULL || p0 + u < end;
@@ -431,7 +434,9 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 }
             }
         }
-        load_meta(pn, jn, w1n, w2n);  // past the line it rereads the last entry
+        if constexpr (PF) {
+            if (pn < end) load_meta(pn, std::false_type{}, jn, w1n, w2n);  // one clamped form: no divergence
+        }
         if (partial) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -540,16 +545,20 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         int32_t j[U], jn[U];
         Acc w1[U], w2[U], w1n[U], w2n[U];
         int32_t p0 = begin + gidx * U;
-        if (p0 < end) load_meta(p0, j, w1, w2);
+        if constexpr (PF) {
+            if (p0 < end) load_meta(p0, std::false_type{}, j, w1, w2);
+        }
         for (; p0 < end; p0 += U * GPL) {
             const int32_t pn = p0 + U * GPL;
             if (p0 + U <= end) run_batch(p0, std::true_type{}, j, w1, w2, pn, jn, w1n, w2n);
             else run_batch(p0, std::false_type{}, j, w1, w2, pn, jn, w1n, w2n);
+            if constexpr (PF) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                j[u] = jn[u];
-                w1[u] = w1n[u];
-                w2[u] = w2n[u];
+                for (int u = 0; u < U; ++u) {
+                    j[u] = jn[u];
+                    w1[u] = w1n[u];
+                    w2[u] = w2n[u];
+                }
             }
         }
     }

@@ -157,18 +157,24 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
     for (int e = 0; e < E; ++e) acc[e] = Acc(0);
     Acc m = neg_inf<Acc>(), l = Acc(0);
 
-    for (int32_t p0 = begin; p0 < end; p0 += U) {
-        int32_t j[U];
-        bool ok[U];
-        Acc sc[U];
+    // Column indices and edge values of the batch at p0; entries past `end` reread the
+    // last entry, so every load is in bounds.
+    auto load_meta = [&](int32_t p0, int32_t *j, Acc *sc) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
-            ok[u] = p < end;
-            const int32_t pc = ok[u] ? p : end - 1;
+            const int32_t pc = p < end ? p : end - 1;
             j[u] = idx[pc];
             sc[u] = val ? val[pc] : Acc(1);
         }
+    };
+    int32_t j[U], jn[U];
+    Acc sc[U], scn[U];
+    if (begin < end) load_meta(begin, j, sc);
+    for (int32_t p0 = begin; p0 < end; p0 += U) {
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = p0 + u < end;
         Raw<TH, VW> g[U][NV];
         Acc tj[U];
 #pragma unroll
@@ -179,6 +185,8 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
                 for (int v = 0; v < NV; ++v) g[u][v].load(H + (size_t)j[u] * r + off[v]);
             }
         }
+        // the next batch's operands arrive while this batch waits for its rows
+        if (p0 + U < end) load_meta(p0 + U, jn, scn);
         // LeakyReLU of the sampled score; entries past the end get weight 0 (softmax: -inf)
         Acc ev[U];
 #pragma unroll
@@ -213,6 +221,11 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
             for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int e = 0; e < VW; ++e) acc[v * VW + e] += w[u] * Acc(g[u][v].get(e));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            j[u] = jn[u];
+            sc[u] = scn[u];
         }
     }
 
