@@ -464,12 +464,20 @@ def run_als(args):
     print(json.dumps(out), flush=True)
 
 
-def restore_tuning(P, variants, splits):
-    """Put back an autotuned batch depth and split threshold per orientation."""
+def restore_tuning(P, tuning):
+    """Put back an autotuned configuration (P.tuning): per orientation the split
+    threshold, the line order and the batch depth."""
     from paper_2203_07673_amd import _capi as CA
     for o, k in ((CA.FMM_CSR, "csr"), (CA.FMM_CSC, "csc")):
-        P.set_split(o, splits[k] if splits[k] is not None else NO_SPLIT)
-    P.set_variant(variants["csr"], variants["csc"])
+        t = tuning[k]
+        P.set_split(o, t["long_len"] if t["long_len"] is not None else NO_SPLIT)
+        P.set_line_order(o, t["line_order"])
+    P.set_variant(tuning["csr"]["variant"], tuning["csc"]["variant"])
+
+
+def tuning_arg(tuning):
+    """--tuned form of P.tuning: csr=VARIANT:LONG_LEN:ORDER,csc=... (LONG_LEN 0 = no split)."""
+    return ",".join(f"{k}={t['variant']}:{t['long_len'] or 0}:{int(t['line_order'])}" for k, t in tuning.items())
 
 
 def calibrate_copy(dev):
@@ -489,11 +497,12 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
 
     dev = A.device
     if args.tuned:
-        from paper_2203_07673_amd import _capi as CA
-        vr, vc, lr, lc = (int(x) for x in args.tuned.split(","))
-        for o, ll in ((CA.FMM_CSR, lr), (CA.FMM_CSC, lc)):
-            P.set_split(o, ll if ll > 0 else NO_SPLIT)
-        P.set_variant(vr, vc)
+        tuning = {}
+        for part in args.tuned.split(","):
+            k, v = part.split("=")
+            var, ll, lo = (int(x) for x in v.split(":"))
+            tuning[k] = {"variant": var, "long_len": ll or None, "line_order": bool(lo)}
+        restore_tuning(P, tuning)
     if args.profile_step == "fused_f32":
         step = make_step(A, B, fused=True)
     elif args.profile_step == "unfused_f32":
@@ -505,8 +514,8 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
     t, kt = time_steps(step, args.steps, args.warmup)
     if args.calibrate_copy:
         calibrate_copy(dev)
-    print(json.dumps({"profile_step": args.profile_step, "workload": args.workload, "variants": P.variants,
-                      "splits": P.splits, "ms_per_step": round(t * 1e3, 4),
+    print(json.dumps({"profile_step": args.profile_step, "workload": args.workload, "tuning": P.tuning,
+                      "ms_per_step": round(t * 1e3, 4),
                       "gflops": round(flops / t / 1e9, 1), "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}),
           flush=True)
 
@@ -531,8 +540,8 @@ def main():
                     help="run only this step variant, for profiling (no autotune: the batch depth and split "
                          "threshold come from --tuned, else the defaults)")
     ap.add_argument("--tuned", default="",
-                    help="CSR_VARIANT,CSC_VARIANT,CSR_LONG_LEN,CSC_LONG_LEN as a bench run's autotune chose them "
-                         "(long_len 0 = no split schedule)")
+                    help="csr=VARIANT:LONG_LEN:ORDER,csc=VARIANT:LONG_LEN:ORDER as a bench run's autotune chose "
+                         "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1)")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -622,9 +631,9 @@ def main():
     if args.profile_step:
         profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz)
         return
-    tuned = P.autotune(A, B, G, form="a")
-    splits = P.splits
-    log(f"autotuned batch variants (f32): {tuned}, split thresholds {splits}")
+    P.autotune(A, B, G, form="a")
+    tuning = P.tuning
+    log(f"autotuned (f32): {tuning}")
     step_f32 = make_step(A, B, fused=True)
     log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
     t_step, kt = time_steps(step_f32, args.steps, args.warmup)
@@ -664,13 +673,12 @@ def main():
         log(f"unfused f32 step {t_unf * 1e3:.3f} ms")
         del R_ws, dP_ws
         A16, B16 = F.to_bf16(A), F.to_bf16(B)
-        keep = (dict(tuned), dict(splits))
-        tuned16 = P.autotune(A16, B16, G, form="a")
+        P.autotune(A16, B16, G, form="a")
         t_bf, kt_bf = time_steps(make_step(A16, B16, fused=True), vsteps, 2)
         variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
                                   "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()},
-                                  "batch_variants": tuned16, "split_long_len": P.splits}
-        restore_tuning(P, *keep)
+                                  "tuning_arg": tuning_arg(P.tuning)}
+        restore_tuning(P, tuning)
         log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
         variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
         variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
@@ -711,7 +719,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "r": r, "storage": "f32",
-                   "batch_variants": tuned, "split_long_len": splits,
+                   "tuning": tuning, "tuning_arg": tuning_arg(tuning),
                    "step": "fused FusedMMA forward + adjoint (dA row pass, dB column pass)",
                    "flops_per_step": flops},
         "roofline": roofline,

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 2
+#define FMM_ABI_VERSION 3
 
 typedef enum fmm_status {
     FMM_OK = 0,
@@ -91,6 +91,12 @@ typedef enum fmm_orient { FMM_CSR = 0, FMM_CSC = 1 } fmm_orient;
  * with more than long_len stored entries are cut into chunks that run in parallel and
  * are summed afterwards in chunk order.  n_chunks == 0 disables it.
  *
+ * order: optional processing order of the major lines (from fmm_line_order), a
+ * permutation of [0, major extent); NULL processes lines in index order.  It changes
+ * only which lane group takes which line, never a line's arithmetic, so results are
+ * bit-identical with and without it.  Grouping lines of similar length into the same
+ * wavefront keeps a wavefront from idling behind its longest line.
+ *
  * variant: how many stored entries a lane group keeps in flight per batch (FMM_VARIANT_*).
  * Deep batches suit long, uniform lines; shallow ones use fewer registers, so more lines
  * are in flight at once, which suits many short lines.  FMM_VARIANT_AUTO picks from the
@@ -115,6 +121,7 @@ typedef struct fmm_sparse {
     int32_t variant;           /* FMM_VARIANT_*                                            */
     const int32_t *chunks;     /* [3*n_chunks]: line, begin position, end position       */
     const int32_t *splits;     /* [3*n_splits]: line, first chunk, chunk count           */
+    const int32_t *order;      /* [major extent] line processing order, or NULL          */
 } fmm_sparse;
 
 /* ---------------------------------------------------------------- diagnostics */
@@ -188,6 +195,19 @@ fmm_status fmm_schedule_count(const int32_t *ptr, int32_t nmajor, int32_t long_l
 fmm_status fmm_schedule_fill(const int32_t *ptr, int32_t nmajor, int32_t long_len, int32_t chunk,
                              int32_t *chunks, int32_t *splits, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/*
+ * Line processing order for a descriptor's `order` field (a schedule choice; the paper
+ * balances load by permuting S at random, Section VI).  From ptr[nlines+1] it writes the
+ * permutation order[nlines]: first the lines with at most long_len entries, by
+ * decreasing length (lengths of 1023 and more count as equal), then the longer lines,
+ * which the split schedule processes as chunks; ties keep index order.  A stable radix
+ * sort on the GPU, so the result is unique.  Takes a device workspace of
+ * fmm_line_order_workspace() bytes; asynchronous on `stream`.  long_len >= 1.
+ */
+fmm_status fmm_line_order_workspace(int32_t nlines, size_t *bytes);
+fmm_status fmm_line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, int32_t *order, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
 
 /* Round float32 to bfloat16 storage (nearest, ties to even; NaN -> 0x7FC0). */
 fmm_status fmm_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t stream);

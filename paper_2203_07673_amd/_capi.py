@@ -46,6 +46,7 @@ class fmm_sparse(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("chunks", ctypes.c_void_p),
         ("splits", ctypes.c_void_p),
+        ("order", ctypes.c_void_p),
     ]
 
 
@@ -102,6 +103,8 @@ SIGNATURES = {
     "fmm_validate": [_SP, _P],
     "fmm_csr_to_csc_workspace": [_I32, _I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_csr_to_csc": [_I32, _I32, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P],
+    "fmm_line_order_workspace": [_I32, ctypes.POINTER(_SZ)],
+    "fmm_line_order": [_P, _I32, _I32, _P, _P, _SZ, _P],
     "fmm_schedule_workspace": [_I32, ctypes.POINTER(_SZ)],
     "fmm_schedule_count": [_P, _I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _P, _SZ, _P],
     "fmm_schedule_fill": [_P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P],

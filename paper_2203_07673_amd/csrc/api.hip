@@ -147,6 +147,7 @@ LineArgs base_args(const fmm_sparse *S, int32_t r, void *ws)
     a.long_len = S->long_len;
     a.n_chunks = S->n_chunks;
     a.chunks = S->chunks;
+    a.order = S->order;
     a.partial = ws;
     a.beta = 0.0;
     return a;
@@ -338,6 +339,25 @@ fmm_status fmm_csr_to_csc(int32_t m, int32_t n, int32_t nnz, const int32_t *rowp
     if ((uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
     FMM_HIP(csr_to_csc(m, n, nnz, rowptr, colidx, val, val_dtype == FMM_F64 ? 8 : 4, colptr, rowidx, valT, perm, ws,
                        stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_line_order_workspace(int32_t nlines, size_t *bytes)
+{
+    if (!bytes) return FMM_ERR_NULL;
+    if (nlines < 0) return FMM_ERR_DIM;
+    *bytes = line_order_workspace_bytes(nlines);
+    return FMM_OK;
+}
+
+fmm_status fmm_line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, int32_t *order, void *ws,
+                          size_t ws_bytes, hipStream_t stream)
+{
+    if (nlines < 0 || long_len < 1) return FMM_ERR_DIM;
+    if (nlines == 0) return FMM_OK;
+    if (!ptr || !order) return FMM_ERR_NULL;
+    if (!ws || ws_bytes < line_order_workspace_bytes(nlines) || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    FMM_HIP(line_order(ptr, nlines, long_len, order, ws, stream));
     return FMM_OK;
 }
 

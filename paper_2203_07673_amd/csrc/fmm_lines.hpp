@@ -71,6 +71,7 @@ struct LineArgs {
     const int32_t *chunks;
     void *partial;        // n_chunks x r (Acc)
     int32_t uclass;       // batch depth class, 1 (deep) .. 3 (shallow)
+    const int32_t *order; // line processing order (a permutation of the lines), NULL = index order
 };
 
 // ------------------------------------------------------------------ conversions
@@ -610,8 +611,9 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
         if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.partial) + (size_t)c * r;
         to_partial = true;
     } else {
-        line = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
-        if (line >= a.nlines) return;
+        const int32_t k = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
+        if (k >= a.nlines) return;
+        line = a.order ? a.order[k] : k;
         begin = a.ptr[line];
         end = a.ptr[line + 1];
         if (a.n_chunks > 0 && end - begin > a.long_len) return;

@@ -113,6 +113,7 @@ struct GatArgs {
     int32_t long_len, n_chunks;
     const int32_t *chunks;
     void *partial;  // n_chunks x r sums, then n_chunks x 2 (m, l)
+    const int32_t *order;  // row processing order, NULL = index order
 };
 
 template <class TH, class Acc, int L, int NV, int VW, int U, bool SOFTMAX>
@@ -131,8 +132,9 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
         begin = a.chunks[3 * chunk + 1];
         end = a.chunks[3 * chunk + 2];
     } else {
-        line = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
-        if (line >= a.nlines) return;
+        const int32_t k = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
+        if (k >= a.nlines) return;
+        line = a.order ? a.order[k] : k;
         begin = a.ptr[line];
         end = a.ptr[line + 1];
         if (a.n_chunks > 0 && end - begin > a.long_len) return;
@@ -432,6 +434,7 @@ fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, co
     a.long_len = S->long_len;
     a.n_chunks = S->n_chunks;
     a.chunks = S->chunks;
+    a.order = S->order;
     a.partial = ws;
     const bool softmax = (flags & FMM_GAT_SOFTMAX) != 0;
     const int uc = gat_uclass(S);

@@ -210,6 +210,23 @@ __global__ __launch_bounds__(256) void validate_idx_kernel(int32_t nmajor, int32
     else if (p > ptr[lo] && idx[p - 1] >= j) atomicOr(flag, 2);
 }
 
+// ------------------------------------------------------------------ line order
+
+constexpr int32_t kOrderCap = 1023;   // lengths at or above this sort as equal
+constexpr int32_t kOrderLong = 1024;  // key of lines the split schedule processes as chunks
+constexpr int kOrderBits = 11;        // keys lie in [0, kOrderLong]
+
+// Sort key of each line: shorter lines get larger keys (so an ascending stable sort
+// yields decreasing length), lines longer than long_len the largest.
+__global__ __launch_bounds__(256) void line_key_kernel(const int32_t *__restrict__ ptr, int32_t nlines,
+                                                       int32_t long_len, int32_t *__restrict__ key)
+{
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= nlines) return;
+    const int32_t len = ptr[l + 1] - ptr[l];
+    key[l] = len > long_len ? kOrderLong : kOrderCap - (len < kOrderCap ? len : kOrderCap);
+}
+
 // ------------------------------------------------------------------ split schedule
 
 __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restrict__ ptr, int32_t nmajor, int32_t long_len,
@@ -397,6 +414,52 @@ hipError_t validate(int32_t nmajor, int32_t nminor, int32_t nnz, const int32_t *
     hipLaunchKernelGGL(validate_idx_kernel, dim3((unsigned)(((int64_t)nnz + 255) / 256)), dim3(256), 0, s, nmajor, nminor,
                        nnz, ptr, idx, flag_dev);
     return hipGetLastError();
+}
+
+size_t line_order_workspace_bytes(int64_t nlines)
+{
+    const int64_t nb = (nlines + kSortTile - 1) / kSortTile;
+    size_t b = 4 * align256((size_t)nlines * 4);             // keys, then one key/value pair and one key buffer
+    b += 2 * align256((size_t)(256 * nb) * 4);               // histogram and its scan
+    b += scan_workspace_bytes(256 * nb);
+    return b + 256;
+}
+
+hipError_t line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, int32_t *order, void *ws, hipStream_t s)
+{
+    if (nlines <= 0) return hipSuccess;
+    const int64_t nb = (nlines + kSortTile - 1) / kSortTile;
+    char *w = static_cast<char *>(ws);
+    int32_t *key = reinterpret_cast<int32_t *>(w); w += align256((size_t)nlines * 4);
+    int32_t *ka = reinterpret_cast<int32_t *>(w); w += align256((size_t)nlines * 4);
+    int32_t *va = reinterpret_cast<int32_t *>(w); w += align256((size_t)nlines * 4);
+    int32_t *kb = reinterpret_cast<int32_t *>(w); w += align256((size_t)nlines * 4);
+    int32_t *hist = reinterpret_cast<int32_t *>(w); w += align256((size_t)(256 * nb) * 4);
+    int32_t *hoff = reinterpret_cast<int32_t *>(w); w += align256((size_t)(256 * nb) * 4);
+    void *scan_ws = w;
+    hipLaunchKernelGGL(line_key_kernel, dim3((unsigned)(((int64_t)nlines + 255) / 256)), dim3(256), 0, s, ptr, nlines,
+                       long_len, key);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // two stable 8-bit passes (keys have kOrderBits <= 16 bits); values start as the identity
+    static_assert(kOrderBits <= 16, "two radix passes");
+    const int32_t *kin = key;
+    const int32_t *vin = nullptr;
+    int32_t *kouts[2] = {ka, kb};
+    int32_t *vouts[2] = {va, order};
+    for (int pass = 0; pass < 2; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, (int64_t)nlines, shift,
+                           hist, (int32_t)nb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = exclusive_scan_i32(hist, hoff, 256 * nb, scan_ws, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kouts[pass],
+                           vouts[pass], (int64_t)nlines, shift, (const int32_t *)hoff, (int32_t)nb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kouts[pass];
+        vin = vouts[pass];
+    }
+    return hipSuccess;
 }
 
 size_t schedule_workspace_bytes(int64_t nmajor)

@@ -30,6 +30,7 @@ __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to
 DEFAULT_LONG_LEN = 128
 DEFAULT_CHUNK = 128
 SPLIT_CANDIDATES = (256, 128, 64)
+_NO_SPLIT = (1 << 31) - 1
 
 
 def _stream():
@@ -77,12 +78,17 @@ class Pattern:
     Holds the canonical CSR (rowptr, colidx, val), the stored transposed copy
     (colptr, rowidx, valT, perm) built by the library's GPU transpose, and, where
     some line has more than ``long_len`` entries, the split schedules of both
-    orientations.  The pattern is validated once at construction; later calls
-    trust it.
+    orientations, and each orientation's line processing order by decreasing length
+    (fmm_line_order).  ``line_order`` is True, False or None (the default: on for an
+    orientation whose longest line exceeds four times its mean length, where lines of
+    very different lengths would share wavefronts).  ``autotune`` picks the split
+    threshold, the order and the batch depth per orientation by timing.  The pattern is
+    validated once at construction; later calls trust it.
     """
 
     def __init__(self, rowptr, colidx, val, shape, *, device=None, val_dtype=torch.float32, validate=True,
-                 long_len: int = DEFAULT_LONG_LEN, chunk: int = DEFAULT_CHUNK, split: bool = True):
+                 long_len: int = DEFAULT_LONG_LEN, chunk: int = DEFAULT_CHUNK, split: bool = True,
+                 line_order: Optional[bool] = None):
         device = torch.device(device or "cuda")
         if device.type != "cuda":
             raise ValueError("Pattern lives on a GPU device")
@@ -103,6 +109,7 @@ class Pattern:
         self._csr_sched = None
         self._csc_sched = None
         self._split = split
+        self._orders = {C.FMM_CSR: None, C.FMM_CSC: None}
         self._ws_cache = {}
         if validate:
             C.call("fmm_validate", ctypes.byref(self._desc(C.FMM_CSR, with_sched=False)), _stream())
@@ -110,6 +117,13 @@ class Pattern:
         if split:
             self._csr_sched = self._schedule(self.rowptr, self.m, long_len, chunk)
             self._csc_sched = self._schedule(self.colptr, self.n, long_len, chunk)
+        for o in (C.FMM_CSR, C.FMM_CSC):
+            on = line_order
+            if on is None:
+                nl = self.m if o == C.FMM_CSR else self.n
+                on = nl > 0 and self.max_line(o) > 4.0 * self.nnz / nl
+            if on:
+                self._orders[o] = self._order(o, self._long_len(o))
         self.csr = self._desc(C.FMM_CSR)
         self.csc = self._desc(C.FMM_CSC)
 
@@ -153,6 +167,43 @@ class Pattern:
         return {"long_len": long_len, "chunk": chunk, "n_chunks": nch.value, "n_splits": nsp.value,
                 "chunks": chunks, "splits": splits}
 
+    def _order(self, orient, long_len):
+        """Line processing order of one orientation (device int32 permutation)."""
+        ptr, nlines = (self.rowptr, self.m) if orient == C.FMM_CSR else (self.colptr, self.n)
+        order = torch.empty(max(1, nlines), dtype=torch.int32, device=self.device)
+        bytes_ = ctypes.c_size_t(0)
+        C.call("fmm_line_order_workspace", nlines, ctypes.byref(bytes_))
+        ws = torch.empty(max(1, bytes_.value), dtype=torch.uint8, device=self.device)
+        C.call("fmm_line_order", _ptr(ptr), nlines, max(1, min(long_len, _NO_SPLIT)), _ptr(order), _ptr(ws),
+               bytes_.value, _stream())
+        torch.cuda.current_stream().synchronize()
+        return order
+
+    def _long_len(self, orient):
+        sch = self._csr_sched if orient == C.FMM_CSR else self._csc_sched
+        return sch["long_len"] if sch is not None else _NO_SPLIT
+
+    def _refresh(self, orient):
+        """Rebuild one orientation's descriptor from its schedule and order, keeping the batch depth."""
+        if orient == C.FMM_CSR:
+            keep = self.csr.variant
+            self.csr = self._desc(C.FMM_CSR)
+            self.csr.variant = keep
+        else:
+            keep = self.csc.variant
+            self.csc = self._desc(C.FMM_CSC)
+            self.csc.variant = keep
+
+    def set_line_order(self, orient, enabled: bool):
+        """Process one orientation's lines by decreasing length (True) or in index order."""
+        self._orders[orient] = self._order(orient, self._long_len(orient)) if enabled else None
+        self._refresh(orient)
+
+    @property
+    def orders(self):
+        """Line processing order of each orientation (None when disabled)."""
+        return {"csr": self._orders[C.FMM_CSR], "csc": self._orders[C.FMM_CSC]}
+
     def _desc(self, orient, with_sched=True):
         d = C.fmm_sparse()
         d.orient = orient
@@ -167,6 +218,8 @@ class Pattern:
         if with_sched and sch is not None:
             d.long_len, d.n_chunks, d.n_splits = sch["long_len"], sch["n_chunks"], sch["n_splits"]
             d.chunks, d.splits = sch["chunks"].data_ptr(), sch["splits"].data_ptr()
+        if with_sched and self._orders.get(orient) is not None:
+            d.order = self._orders[orient].data_ptr()
         return d
 
     def descriptor(self, orient, schedule=True):
@@ -177,17 +230,16 @@ class Pattern:
 
     def set_split(self, orient, long_len, chunk=None):
         """Rebuild one orientation's split schedule: lines longer than long_len are cut
-        into chunks of `chunk` (default long_len) entries.  The batch depth is kept."""
-        keep = self.csr.variant if orient == C.FMM_CSR else self.csc.variant
+        into chunks of `chunk` (default long_len) entries.  The batch depth and the
+        order setting are kept."""
         chunk = chunk or long_len
         if orient == C.FMM_CSR:
             self._csr_sched = self._schedule(self.rowptr, self.m, long_len, chunk)
-            self.csr = self._desc(C.FMM_CSR)
-            self.csr.variant = keep
         else:
             self._csc_sched = self._schedule(self.colptr, self.n, long_len, chunk)
-            self.csc = self._desc(C.FMM_CSC)
-            self.csc.variant = keep
+        if self._orders[orient] is not None:  # the order places split lines last
+            self._orders[orient] = self._order(orient, self._long_len(orient))
+        self._refresh(orient)
 
     def max_line(self, orient):
         ptr = self.rowptr if orient == C.FMM_CSR else self.colptr
@@ -212,12 +264,13 @@ class Pattern:
     def variants(self):
         return {"csr": self.csr.variant, "csc": self.csc.variant}
 
-    def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES):
+    def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES, orders=(False, True)):
         """Time FusedMMA (form "a") or FusedMMB ("b") forward and adjoint on these operands
-        and keep, per orientation, the fastest split threshold (from split_candidates,
-        where some line is longer) and batch depth.  The library's fmm_autotune picks the
-        depth for each threshold; the forward times the orientation the forward runs on,
-        the two-row adjoint pass the other one."""
+        and keep, per orientation, the fastest combination of split threshold (from
+        split_candidates, where some line is longer), line order (from `orders`) and
+        batch depth.  The library's fmm_autotune picks the depth for each combination;
+        the forward times the orientation the forward runs on, the two-row adjoint pass
+        the other one."""
         r = A.shape[1]
         dcode, odt = _common(self, A, B)
         rows_out = self.m if form == "a" else self.n
@@ -256,29 +309,38 @@ class Pattern:
 
         longest = max(self.max_line(C.FMM_CSR), self.max_line(C.FMM_CSC))
         cands = [ll for ll in split_candidates if ll < longest] if self._split else []
-        if len(cands) <= 1:
-            if cands:
-                for o in (C.FMM_CSR, C.FMM_CSC):
-                    self.set_split(o, cands[0])
-            tune_depth()
-            return self.variants
+        combos = [(lo, ll) for lo in orders for ll in (cands or [None])]
         best = {}
-        for ll in cands:
+        for lo, ll in combos:
             for o in (C.FMM_CSR, C.FMM_CSC):
-                self.set_split(o, ll)
+                if ll is not None:
+                    self.set_split(o, ll)
+                self.set_line_order(o, lo)
             tune_depth()
+            if len(combos) == 1:
+                return self.variants
             for o, fn in ((own, fwd), (other, two_row)):
                 ms = time_it(fn)
                 v = self.csr.variant if o == C.FMM_CSR else self.csc.variant
                 if o not in best or ms < best[o][0]:
-                    best[o] = (ms, ll, v)
-        for o, (_, ll, v) in best.items():
-            self.set_split(o, ll)
+                    best[o] = (ms, lo, ll, v)
+        for o, (_, lo, ll, v) in best.items():
+            if ll is not None:
+                self.set_split(o, ll)
+            self.set_line_order(o, lo)
             if o == C.FMM_CSR:
                 self.csr.variant = v
             else:
                 self.csc.variant = v
         return self.variants
+
+    @property
+    def tuning(self):
+        """Per orientation: batch depth, split threshold (None: no split schedule) and
+        whether the line order is on."""
+        sp = self.splits
+        return {k: {"variant": (self.csr if k == "csr" else self.csc).variant, "long_len": sp[k],
+                    "line_order": self.orders[k] is not None} for k in ("csr", "csc")}
 
     @property
     def splits(self):

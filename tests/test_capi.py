@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(lib, n), n
         assert n in C.SIGNATURES, n
-    assert lib.fmm_abi_version() == 2
+    assert lib.fmm_abi_version() == 3
 
 
 def test_status_strings():
@@ -162,3 +162,19 @@ def test_batch_plan_argument_errors():
     assert lib.fmm_batch_launch(None, None) == -1
     assert lib.fmm_batch_autotune(None, None) == -1
     assert lib.fmm_batch_set_schedule(None, 1, 0, 0, 0) == -1
+
+
+def test_line_order_argument_errors():
+    lib = C.load()
+    nb = ctypes.c_size_t(0)
+    assert lib.fmm_line_order_workspace(-1, ctypes.byref(nb)) == -2
+    assert lib.fmm_line_order_workspace(10, None) == -1
+    assert lib.fmm_line_order_workspace(100000, ctypes.byref(nb)) == 0 and nb.value >= 4 * 100000
+    need = nb.value
+    assert lib.fmm_line_order(FAKE, -1, 8, FAKE, FAKE, need, None) == -2
+    assert lib.fmm_line_order(FAKE, 100000, 0, FAKE, FAKE, need, None) == -2      # long_len >= 1
+    assert lib.fmm_line_order(None, 100000, 8, FAKE, FAKE, need, None) == -1
+    assert lib.fmm_line_order(FAKE, 100000, 8, None, FAKE, need, None) == -1
+    assert lib.fmm_line_order(FAKE, 100000, 8, FAKE, FAKE, need - 1, None) == -7  # workspace too small
+    assert lib.fmm_line_order(FAKE, 100000, 8, FAKE, FAKE + 4, need, None) == -7  # misaligned workspace
+    assert lib.fmm_line_order(None, 0, 8, None, None, 0, None) == 0              # nothing to order

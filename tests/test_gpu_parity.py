@@ -451,3 +451,59 @@ def test_patterns_without_entries(m, n):
         assert not host(gA).any() and not host(gB).any()
     assert F.sddmm_raw(P, Ad, Bd).numel() == 0
     assert not host(F.spmm_a_raw(P, Bd)).any() and not host(F.spmm_b_raw(P, Ad)).any()
+
+
+def _order_ref(ptr, long_len):
+    lens = np.diff(np.asarray(ptr, np.int64))
+    key = np.where(lens > long_len, 1024, 1023 - np.minimum(lens, 1023))
+    return np.argsort(key, kind="stable")
+
+
+@pytest.mark.parametrize("case", ["er300x200_d9", "rmat10", "tiny_dense"])
+def test_line_order_exact(case):
+    """fmm_line_order: lines up to long_len by decreasing length, then the split ones,
+    ties in index order (a stable sort, so the permutation is unique)."""
+    S = dict(CASES)[case]()
+    log(f"line order {case}")
+    for ll in (16, 1 << 30):
+        P = _pattern(S, long_len=ll, chunk=min(ll, 16), line_order=True)
+        colptr = oracle.csr_to_csc(S)[0]
+        assert np.array_equal(P.orders["csr"].cpu().numpy()[:S.m], _order_ref(S.rowptr, ll))
+        assert np.array_equal(P.orders["csc"].cpu().numpy()[:S.n], _order_ref(colptr, ll))
+    # lengths of 1023 and more sort as equal
+    rp = np.array([0, 1500, 1503, 2603, 2603], np.int32)
+    ci = np.concatenate([np.arange(1500), np.arange(3), np.arange(1100)]).astype(np.int32)
+    S2 = CsrPattern(4, 2000, rp, ci, np.ones(len(ci), np.float32))
+    P2 = _pattern(S2, split=False, line_order=True)
+    assert P2.orders["csr"].cpu().numpy().tolist() == [0, 2, 1, 3]
+
+
+def test_line_order_gives_identical_results():
+    """The order only moves lines between lane groups: every output is bit-identical."""
+    S = rmat(11, 8, seed=195)
+    r = 64
+    A, B = _inputs(S, r, 196, torch.float32)
+    G = dense_normal(S.m, r, 197)
+    Gb = dense_normal(S.n, r, 198)
+    log("line order identical results")
+    Po = _pattern(S, long_len=64, chunk=32, line_order=True)
+    Pn = _pattern(S, long_len=64, chunk=32, line_order=False)
+    assert Po.csr.order and not Pn.csr.order
+    for dtype in (torch.float32, torch.bfloat16):
+        Ad, Bd = _to_dev(A, dtype), _to_dev(B, dtype)
+        for fused in (True, False):
+            outs = []
+            for P in (Po, Pn):
+                Ca, Ra = F.fusedmm_a_raw(P, Ad, Bd, fused=fused)
+                Cb, _ = F.fusedmm_b_raw(P, Ad, Bd, fused=fused)
+                gA, gB = F.fusedmm_a_backward_raw(P, Ad, Bd, dev(G), fused=fused, R_ws=None if fused else Ra)
+                hA, hB = F.fusedmm_b_backward_raw(P, Ad, Bd, dev(Gb), fused=fused,
+                                                  R_ws=None if fused else F.fusedmm_b_raw(P, Ad, Bd, fused=False)[1])
+                outs.append([Ca, Cb, gA, gB, hA, hB, F.sddmm_raw(P, Ad, Bd), F.spmm_a_raw(P, Bd),
+                             F.spmm_b_raw(P, Ad)])
+            for x, y in zip(*outs):
+                assert torch.equal(x, y)
+    a1 = dev(dense_normal(1, r, 199, sigma=r ** -0.5)[0])
+    a2 = dev(dense_normal(1, r, 200, sigma=r ** -0.5)[0])
+    Hd = dev(B)
+    assert torch.equal(F.gat_forward(Po, Hd, a1, a2), F.gat_forward(Pn, Hd, a1, a2))
