@@ -66,7 +66,7 @@ typedef enum fmm_status {
                                    monotone / not starting at 0 / not ending at nnz     */
     FMM_ERR_NONCANONICAL = -6,  /* fmm_validate: duplicate or unsorted minor indices    */
     FMM_ERR_WORKSPACE = -7,     /* workspace missing or smaller than required           */
-    FMM_ERR_UNSUPPORTED = -8,   /* valid request this build does not implement          */
+    FMM_ERR_UNSUPPORTED = -8,   /* valid request this library does not implement        */
     FMM_ERR_HIP = -9,           /* a HIP runtime call failed                           */
     FMM_ERR_STATE = -10         /* batch plan not in the state the call needs (no graph
                                    captured, or captured before the latest autotune)   */
