@@ -215,6 +215,20 @@ def fusedmm_b_backward(S, A, B, dC):
     return dA, dB
 
 
+def fusedmm_a_backward_values(S, A, B, dC, rows=None):
+    """Gradient of L with respect to S's stored values for C = FusedMMA(S, A, B), the
+    adjoint with learned edge values.  C_i = sum_j S_ij P_ij B_j with P = A B^T, so
+    dL/dS_ij = P_ij <dC_i:, B_j:>: the pattern's SDDMM of A, B times that of dC, B (CSR
+    order; with ``rows`` only those rows' entries, others 0)."""
+    return sddmm(S, A, B, val=None, rows=rows) * sddmm(S, dC, B, val=None, rows=rows)
+
+
+def fusedmm_b_backward_values(S, A, B, dC, rows=None):
+    """Gradient with respect to S's stored values for C' = FusedMMB(S, A, B):
+    C'_j = sum_i S_ij P_ij A_i, so dL/dS_ij = P_ij <A_i:, dC_j:> (CSR order)."""
+    return sddmm(S, A, B, val=None, rows=rows) * sddmm(S, A, dC, val=None, rows=rows)
+
+
 def sddmm_backward(S, A, B, dR):
     """Adjoint of R = SDDMM(A, B, S) (stored values R[p]) w.r.t. A and B:
     dA = (S * dR) B = SpMMA(S*dR, B), dB = (S * dR)^T A = SpMMB(S*dR, A)."""

@@ -366,3 +366,67 @@ def test_bf16_round_matches_torch():
     got = oracle.bf16_round(x)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     assert np.isnan(oracle.bf16_round(np.array([np.nan], np.float32))[0])
+
+
+# ------------------------------------------------------------ gradient w.r.t. S's values
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_value_gradient_vs_dense_torch_autograd(seed):
+    """dL/dS at the stored entries, against torch autograd through the dense masked
+    products (FusedMMA: C = (S*(A B^T)) B; FusedMMB: C' = (S*(A B^T))^T A)."""
+    case = tiny_case(13, 11, 5, 0.3, seed=80 + seed)
+    S, A, B, G = case["S"], case["A"], case["B"], case["G"]
+    Gb = np.random.default_rng(90 + seed).standard_normal((11, 5))
+    rows = torch.tensor(np.repeat(np.arange(S.m), np.diff(S.rowptr)))
+    cols = torch.tensor(S.colidx.astype(np.int64))
+    for variant in ("a", "b"):
+        st = torch.tensor(np.asarray(S.val, np.float64), requires_grad=True)
+        Sd = torch.zeros(S.m, S.n, dtype=torch.float64).index_put((rows, cols), st)
+        At, Bt = torch.tensor(A), torch.tensor(B)
+        R = Sd * (At @ Bt.T)
+        if variant == "a":
+            (R @ Bt * torch.tensor(G)).sum().backward()
+            ds = oracle.fusedmm_a_backward_values(S, A, B, G)
+        else:
+            (R.T @ At * torch.tensor(Gb)).sum().backward()
+            ds = oracle.fusedmm_b_backward_values(S, A, B, Gb)
+        close(ds, st.grad.numpy(), 100)
+
+
+def test_value_gradient_central_differences():
+    # L = sum(C * G) is linear in S's values, so central differences are exact up to rounding
+    S = er_exact_degree(256, 256, 8, seed=84, val_dtype=np.float64)
+    A, B = dense_normal(256, 8, 85, dtype=np.float64), dense_normal(256, 8, 86, dtype=np.float64)
+    G = dense_normal(256, 8, 87, dtype=np.float64)
+    for variant in ("a", "b"):
+        fwd = oracle.fusedmm_a if variant == "a" else oracle.fusedmm_b
+        ds = (oracle.fusedmm_a_backward_values if variant == "a" else oracle.fusedmm_b_backward_values)(S, A, B, G)
+        h = 0.5
+        rng = np.random.default_rng(88)
+        for p in rng.choice(S.nnz, 200, replace=False):
+            old = S.val[p]
+            S.val[p] = old + h
+            lp = float((fwd(S, A, B) * G).sum())
+            S.val[p] = old - h
+            lm = float((fwd(S, A, B) * G).sum())
+            S.val[p] = old
+            assert abs((lp - lm) / (2 * h) - ds[p]) <= 1e-10 * max(1.0, abs(ds[p]))
+
+
+def test_value_gradient_identities():
+    """sum_p S_p dS_p = <C, dC> (C is linear in S), and the rows form matches the full one."""
+    S = rmat(9, 8, seed=89, val_dtype=np.float64)
+    r = 6
+    A, B = dense_normal(S.m, r, 90, dtype=np.float64), dense_normal(S.n, r, 91, dtype=np.float64)
+    G, Gb = dense_normal(S.m, r, 92, dtype=np.float64), dense_normal(S.n, r, 93, dtype=np.float64)
+    da = oracle.fusedmm_a_backward_values(S, A, B, G)
+    db = oracle.fusedmm_b_backward_values(S, A, B, Gb)
+    ca, cb = float((oracle.fusedmm_a(S, A, B) * G).sum()), float((oracle.fusedmm_b(S, A, B) * Gb).sum())
+    assert abs(float(np.dot(S.val, da)) - ca) <= 1e-10 * max(1.0, float(np.abs(S.val) @ np.abs(da)))
+    assert abs(float(np.dot(S.val, db)) - cb) <= 1e-10 * max(1.0, float(np.abs(S.val) @ np.abs(db)))
+    rows = np.array([0, 5, 17, S.m - 1])
+    part = oracle.fusedmm_a_backward_values(S, A, B, G, rows=rows)
+    keep = np.zeros(S.nnz, bool)
+    for i in rows:
+        keep[S.rowptr[i]:S.rowptr[i + 1]] = True
+    assert np.array_equal(part[keep], da[keep]) and not part[~keep].any()
