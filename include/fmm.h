@@ -197,6 +197,14 @@ fmm_status fmm_schedule_fill(const int32_t *ptr, int32_t nmajor, int32_t long_le
                              hipStream_t stream);
 
 /*
+ * Values of S in another orientation: dst[q] = src[perm[q]] for q < nnz (float32 or
+ * float64 per val_dtype).  With the perm of fmm_csr_to_csc it turns CSR-order values
+ * (new or learned edge values) into the CSC order of the stored transposed copy.
+ */
+fmm_status fmm_gather_values(const int32_t *perm, const void *src, int32_t val_dtype, void *dst, int32_t nnz,
+                             hipStream_t stream);
+
+/*
  * Line processing order for a descriptor's `order` field (a schedule choice; the paper
  * balances load by permuting S at random, Section VI).  From ptr[nlines+1] it writes the
  * permutation order[nlines]: first the lines with at most long_len entries, by
@@ -227,6 +235,8 @@ fmm_status fmm_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s
 #define FMM_OP_SDDMM_BWD 7
 #define FMM_OP_SPMM_A_BWD 8
 #define FMM_OP_SPMM_B_BWD 9
+#define FMM_OP_FUSEDMM_A_BWD_VALUES 10
+#define FMM_OP_FUSEDMM_B_BWD_VALUES 11
 fmm_status fmm_workspace_size(int32_t op, const fmm_sparse *S_csr, const fmm_sparse *S_csc,
                               int32_t r, int32_t dtype, size_t *bytes);
 
@@ -320,6 +330,34 @@ fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
                                   const void *B, const void *dC, int32_t r, int32_t dtype,
                                   void *dA, void *dB, int32_t flags, const void *R_ws, void *dP_ws,
                                   void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Gradient with respect to S's stored values (learned edge values; the paper's attention
+ * application, Section VI-E, trains such values), for C = FusedMMA(S, A, B) = R B with
+ * R = S * P, P = A B^T and upstream gradient dC (rows x r):
+ *   dS_ij = P_ij <dC_i, B_j>                      at every stored entry, CSR order.
+ * dS: nnz values (float32; float64 for FMM_F64).  FMM_FUSED: one pass on S_csr holding
+ * dC_i and A_i, gathering B_j, with both dot products in registers; when dA is non-NULL
+ * the same pass also writes dA = FusedMMA(S, dC, B) (the row pass of
+ * fmm_fusedmm_a_backward), so a training step with learned values costs no extra pass.
+ * FMM_UNFUSED: two SDDMM passes (P into dS, then dS *= <dC_i, B_j> in place); dA must
+ * be NULL.  ws: split partials of S_csr when dA is written (FMM_OP_FUSEDMM_A_BWD_VALUES).
+ */
+fmm_status fmm_fusedmm_a_backward_values(const fmm_sparse *S_csr, const void *A, const void *B, const void *dC,
+                                         int32_t r, int32_t dtype, void *dS, void *dA, int32_t flags, void *ws,
+                                         size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The same for C' = FusedMMB(S, A, B) = R^T A, upstream gradient dC (cols x r):
+ *   dS_ij = P_ij <A_i, dC_j>                      CSR order.
+ * FMM_FUSED: one pass on the transposed copy S_csc holding dC_j and B_j, gathering A_i,
+ * writing dS through S_csc->perm and, when dB is non-NULL, dB = FusedMMB(S, A, dC) (the
+ * column pass of fmm_fusedmm_b_backward).  FMM_UNFUSED: two SDDMM passes on S_csr; dB
+ * must be NULL.  ws: split partials of S_csc when dB is written.
+ */
+fmm_status fmm_fusedmm_b_backward_values(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
+                                         const void *B, const void *dC, int32_t r, int32_t dtype, void *dS,
+                                         void *dB, int32_t flags, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Adjoint of R = SDDMM(A, B, S) with upstream gradient dR (nnz, CSR order):

@@ -14,9 +14,11 @@ from .fusedmm import (  # noqa: F401
     dtype_code,
     fusedmm_a,
     fusedmm_a_backward_raw,
+    fusedmm_a_backward_values_raw,
     fusedmm_a_raw,
     fusedmm_b,
     fusedmm_b_backward_raw,
+    fusedmm_b_backward_values_raw,
     fusedmm_b_raw,
     gat_edge_values,
     gat_forward,

@@ -21,7 +21,8 @@ FMM_CSR, FMM_CSC = 0, 1
 FMM_FUSED, FMM_UNFUSED = 0, 1
 FMM_VARIANT_AUTO, FMM_VARIANT_DEEP, FMM_VARIANT_MEDIUM, FMM_VARIANT_SHALLOW = 0, 1, 2, 3
 (FMM_OP_SDDMM, FMM_OP_SPMM_A, FMM_OP_SPMM_B, FMM_OP_FUSEDMM_A, FMM_OP_FUSEDMM_B, FMM_OP_FUSEDMM_A_BWD,
- FMM_OP_FUSEDMM_B_BWD, FMM_OP_SDDMM_BWD, FMM_OP_SPMM_A_BWD, FMM_OP_SPMM_B_BWD) = range(10)
+ FMM_OP_FUSEDMM_B_BWD, FMM_OP_SDDMM_BWD, FMM_OP_SPMM_A_BWD, FMM_OP_SPMM_B_BWD,
+ FMM_OP_FUSEDMM_A_BWD_VALUES, FMM_OP_FUSEDMM_B_BWD_VALUES) = range(12)
 
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_ERR_NULL", -2: "FMM_ERR_DIM", -3: "FMM_ERR_DTYPE", -4: "FMM_ERR_ORIENT",
                 -5: "FMM_ERR_INDEX", -6: "FMM_ERR_NONCANONICAL", -7: "FMM_ERR_WORKSPACE",
@@ -103,6 +104,9 @@ SIGNATURES = {
     "fmm_validate": [_SP, _P],
     "fmm_csr_to_csc_workspace": [_I32, _I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_csr_to_csc": [_I32, _I32, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P],
+    "fmm_gather_values": [_P, _P, _I32, _P, _I32, _P],
+    "fmm_fusedmm_a_backward_values": [_SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
+    "fmm_fusedmm_b_backward_values": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
     "fmm_line_order_workspace": [_I32, ctypes.POINTER(_SZ)],
     "fmm_line_order": [_P, _I32, _I32, _P, _P, _SZ, _P],
     "fmm_schedule_workspace": [_I32, ctypes.POINTER(_SZ)],

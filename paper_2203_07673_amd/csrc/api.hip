@@ -179,6 +179,8 @@ hipError_t run(int path, char hk, char g1k, char g2k, const LineArgs &a, const f
         if (hk == 'O' && g1k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
     } else if constexpr (OP == OP_FUSED2) {
         if (hk == 'S' && g1k == 'S' && g2k == 'O') return launch_lines<OP, Sb, Sb, Of, float>(a, ns, sp, hint(), st);
+    } else if constexpr (OP == OP_FUSED1S) {  // g2k: kind of the second held row
+        if (hk == 'O' && g1k == 'S' && g2k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
     }
     (void)g2k;
     return hipErrorInvalidValue;
@@ -222,6 +224,28 @@ fmm_status check_ws2(const fmm_sparse *a, const fmm_sparse *b, int32_t r, size_t
     const size_t need = max_partial(a, b, r, obytes);
     if (need == 0) return FMM_OK;
     if (!ws || ws_bytes < need || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
+    return FMM_OK;
+}
+
+// dS = P * <X_i, Y_j> on S_csr in two SDDMM passes: P = <A_i, B_j> into dS, then
+// dS[p] *= <X_i, Y_j> in place (each entry is read and written by the same lane group).
+fmm_status values_unfused(const fmm_sparse *S_csr, const Kinds &k, const void *A, const void *B, char xk,
+                                 const void *X, char yk, const void *Y, int32_t r, void *dS, hipStream_t stream)
+{
+    fmm_sparse Sx = *S_csr;
+    Sx.n_splits = 0;
+    LineArgs s = base_args(S_csr, r, nullptr);
+    s.val = nullptr;
+    s.H = A;
+    s.G1 = B;
+    s.out = dS;
+    FMM_HIP(run<OP_SDDMM>(k.path, 'S', 'S', 'S', s, &Sx, stream));
+    LineArgs t = base_args(S_csr, r, nullptr);
+    t.val = dS;
+    t.H = X;
+    t.G1 = Y;
+    t.out = dS;
+    FMM_HIP(run<OP_SDDMM>(k.path, xk, yk, yk, t, &Sx, stream));
     return FMM_OK;
 }
 
@@ -342,6 +366,17 @@ fmm_status fmm_csr_to_csc(int32_t m, int32_t n, int32_t nnz, const int32_t *rowp
     return FMM_OK;
 }
 
+fmm_status fmm_gather_values(const int32_t *perm, const void *src, int32_t val_dtype, void *dst, int32_t nnz,
+                             hipStream_t stream)
+{
+    if (nnz < 0) return FMM_ERR_DIM;
+    if (val_dtype != FMM_F32 && val_dtype != FMM_F64) return FMM_ERR_DTYPE;
+    if (nnz == 0) return FMM_OK;
+    if (!perm || !src || !dst) return FMM_ERR_NULL;
+    FMM_HIP(gather_values(perm, src, dst, nnz, val_dtype == FMM_F64 ? 8 : 4, stream));
+    return FMM_OK;
+}
+
 fmm_status fmm_line_order_workspace(int32_t nlines, size_t *bytes)
 {
     if (!bytes) return FMM_ERR_NULL;
@@ -417,6 +452,8 @@ fmm_status fmm_workspace_size(int32_t op, const fmm_sparse *S_csr, const fmm_spa
     case FMM_OP_SDDMM_BWD:
     case FMM_OP_SPMM_A_BWD:
     case FMM_OP_SPMM_B_BWD: *bytes = max_partial(S_csr, S_csc, r, k.obytes); return FMM_OK;
+    case FMM_OP_FUSEDMM_A_BWD_VALUES: *bytes = partial_bytes(S_csr, r, k.obytes); return FMM_OK;
+    case FMM_OP_FUSEDMM_B_BWD_VALUES: *bytes = partial_bytes(S_csc, r, k.obytes); return FMM_OK;
     default: return FMM_ERR_DIM;
     }
 }
@@ -690,6 +727,66 @@ fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
         a.out = dA;
         FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', 'O', a, S_csr, stream));
     }
+    return FMM_OK;
+}
+
+fmm_status fmm_fusedmm_a_backward_values(const fmm_sparse *S_csr, const void *A, const void *B, const void *dC,
+                                         int32_t r, int32_t dtype, void *dS, void *dA, int32_t flags, void *ws,
+                                         size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S_csr, FMM_CSR));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    FMM_TRY(check_dense(dC, m, k.obytes, r));
+    if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
+    if (S_csr->nnz > 0 && !dS) return FMM_ERR_NULL;
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (dA) return FMM_ERR_UNSUPPORTED;
+        return values_unfused(S_csr, k, A, B, 'O', dC, 'S', B, r, dS, stream);
+    }
+    if (dA) FMM_TRY(check_ws(S_csr, r, k.obytes, ws, ws_bytes));
+    LineArgs a = base_args(S_csr, r, ws);  // held dC_i and A_i, gathered B_j
+    a.H = dC;
+    a.H2 = A;
+    a.G1 = B;
+    a.out = dA;
+    a.values = dS;
+    FMM_HIP(run<OP_FUSED1S>(k.path, 'O', 'S', 'S', a, S_csr, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_fusedmm_b_backward_values(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
+                                         const void *B, const void *dC, int32_t r, int32_t dtype, void *dS,
+                                         void *dB, int32_t flags, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FMM_TRY(check_pair(S_csr, S_csc));
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    const int32_t m = S_csr->rows, n = S_csr->cols;
+    FMM_TRY(check_dense(A, m, k.sbytes, r));
+    FMM_TRY(check_dense(B, n, k.sbytes, r));
+    FMM_TRY(check_dense(dC, n, k.obytes, r));
+    if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
+    if (S_csr->nnz > 0 && !dS) return FMM_ERR_NULL;
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (flags == FMM_UNFUSED) {
+        if (dB) return FMM_ERR_UNSUPPORTED;
+        return values_unfused(S_csr, k, A, B, 'S', A, 'O', dC, r, dS, stream);
+    }
+    if (S_csc->nnz > 0 && !S_csc->perm) return FMM_ERR_NULL;
+    if (dB) FMM_TRY(check_ws(S_csc, r, k.obytes, ws, ws_bytes));
+    LineArgs a = base_args(S_csc, r, ws);  // held dC_j and B_j, gathered A_i; dS through perm
+    a.H = dC;
+    a.H2 = B;
+    a.G1 = A;
+    a.out = dB;
+    a.values = dS;
+    a.operm = S_csc->perm;
+    FMM_HIP(run<OP_FUSED1S>(k.path, 'O', 'S', 'S', a, S_csc, stream));
     return FMM_OK;
 }
 

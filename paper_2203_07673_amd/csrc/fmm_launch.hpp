@@ -85,7 +85,7 @@ hipError_t launch_lines(const LineArgs &a, int32_t n_splits, const int32_t *spli
         }
     }
     if (e != hipSuccess) return e;
-    if (OP != OP_SDDMM && n_splits > 0) {
+    if (OP != OP_SDDMM && n_splits > 0 && a.out != nullptr) {
         const int64_t total = (int64_t)n_splits * a.r;
         const int64_t nb = (total + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((merge_kernel<Acc>), dim3((unsigned)nb), dim3(kBlock), 0, stream, splits, n_splits, a.r,

@@ -4,7 +4,7 @@
 // time (a row of the CSR, or a column of the stored transposed copy), touching for
 // each entry p = (line, idx[p]) one row of a "held" dense matrix H (the line's own
 // row, kept in registers) and one gathered row of G1 (and G2).  This is the shared
-// access pattern of SDDMM and SpMM the paper points out in Section IV-A.  The five
+// access pattern of SDDMM and SpMM the paper points out in Section IV-A.  The six
 // operations differ only in what they do per entry:
 //
 //   OP_SDDMM  : R[p]    = beta R[p] + w_p <H_line, G1_j>                  (Eq. (1))
@@ -14,6 +14,9 @@
 //                                                                           Section IV-B)
 //   OP_FUSED2 : out_line = beta out + sum_p w_p (<H,G2_j> G1_j + <H,G1_j> G2_j)
 //               (the column pass of the adjoints: both sampled products recomputed)
+//   OP_FUSED1S: OP_FUSED1 plus, per entry, V[p] = <H_line, G1_j> <H2_line, G1_j> with a
+//               second held row H2 (the gradient with respect to S's values, written with
+//               the adjoint row pass; out may be NULL)
 //
 // Work decomposition.  A group of L lanes (L | 64) owns one line; lane l holds
 // elements k = (v*L + l)*VW + e (v < NV, e < VW) of each r-vector, so one vector
@@ -47,7 +50,7 @@ template <> __device__ __forceinline__ const float *unit_value<float>() { return
 template <> __device__ __forceinline__ const double *unit_value<double>() { return kUnitD; }
 __device__ __forceinline__ const int32_t *zero_index() { return kZeroIdx; }
 
-enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4 };
+enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4, OP_FUSED1S = 5 };
 
 constexpr int kBlock = 256;
 
@@ -64,7 +67,9 @@ struct LineArgs {
     const void *H;
     const void *G1;
     const void *G2;
-    void *out;            // lines x r (Acc), or nnz (Acc) for OP_SDDMM
+    const void *H2;       // second held matrix (TG2 elements), OP_FUSED1S
+    void *out;            // lines x r (Acc), or nnz (Acc) for OP_SDDMM; may be NULL for OP_FUSED1S
+    void *values;         // nnz per-entry output (Acc) of OP_FUSED1S, through operm when non-NULL
     double beta;
     int32_t long_len;
     int32_t n_chunks;
@@ -315,7 +320,8 @@ struct LineOperands {
     const void *H;
     const void *G1;
     const void *G2;
-    void *R;  // OP_SDDMM output (nnz)
+    const void *H2;  // OP_FUSED1S second held matrix
+    void *R;         // per-entry output (nnz): OP_SDDMM, OP_FUSED1S
     int32_t r;
     double beta;
 };
@@ -350,7 +356,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     const TG1 *__restrict__ G1 = static_cast<const TG1 *>(o.G1);
     const TG2 *__restrict__ G2 = static_cast<const TG2 *>(o.G2);
 
-    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2);
+    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2 || OP == OP_FUSED1S);
+    constexpr bool kHeld2 = (OP == OP_FUSED1S);
     constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
 
     Acc h[E];
@@ -363,6 +370,20 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
             } else {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) h[v * VW + e] = Acc(0);
+            }
+        }
+    }
+
+    Acc h2[kHeld2 ? E : 1];
+    if constexpr (kHeld2) {
+        const TG2 *__restrict__ H2row = static_cast<const TG2 *>(o.H2) + (size_t)line * r;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (act[v]) {
+                Ld<TG2, VW, Acc>::run(H2row + off[v], h2 + v * VW);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) h2[v * VW + e] = Acc(0);
             }
         }
     }
@@ -501,18 +522,33 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                         acc[v * VW + e] += c1 * Acc(g1[u][v].get(e)) + c2 * Acc(g2[u][v].get(e));
             }
         } else {
-            Acc d[U];
+            Acc d[U], dv[kHeld2 ? U : 1];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                Acc s = Acc(0);
+                Acc s = Acc(0), s2 = Acc(0);
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) s += h[v * VW + e] * Acc(g1[u][v].get(e));
+                    for (int e = 0; e < VW; ++e) {
+                        s += h[v * VW + e] * Acc(g1[u][v].get(e));
+                        if constexpr (kHeld2) s2 += h2[v * VW + e] * Acc(g1[u][v].get(e));
+                    }
                 d[u] = s;
+                if constexpr (kHeld2) dv[u] = s2;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) d[u] = group_sum<L>(d[u]);
+            for (int u = 0; u < U; ++u) {
+                d[u] = group_sum<L>(d[u]);
+                if constexpr (kHeld2) dv[u] = group_sum<L>(dv[u]);
+            }
+            if constexpr (kHeld2) {  // V[p] = <H, G1_j> <H2, G1_j>
+                Acc *V = static_cast<Acc *>(o.R);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t p = p0 + u;
+                    if (lane == (u % L) && okv[u]) V[o.operm ? o.operm[p] : p] = d[u] * dv[u];
+                }
+            }
             if constexpr (OP == OP_SDDMM) {
                 Acc *R = static_cast<Acc *>(o.R);
 #pragma unroll
@@ -565,6 +601,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     }
 
     if constexpr (OP != OP_SDDMM) {
+        if (dst == nullptr) return;  // OP_FUSED1S without the row output
         if constexpr (GPL > 1) {
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] = cross_group_sum<L, GPL>(acc[e]);
@@ -608,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
         line = a.chunks[3 * c];
         begin = a.chunks[3 * c + 1];
         end = a.chunks[3 * c + 2];
-        if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.partial) + (size_t)c * r;
+        if (OP != OP_SDDMM && a.out) dst = static_cast<Acc *>(a.partial) + (size_t)c * r;
         to_partial = true;
     } else {
         const int32_t k = (blockIdx.x - nb_chunk_blocks) * GPB + gib;
@@ -617,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
         begin = a.ptr[line];
         end = a.ptr[line + 1];
         if (a.n_chunks > 0 && end - begin > a.long_len) return;
-        if (OP != OP_SDDMM) dst = static_cast<Acc *>(a.out) + (size_t)line * r;
+        if (OP != OP_SDDMM && a.out) dst = static_cast<Acc *>(a.out) + (size_t)line * r;
     }
     LineOperands o;
     o.idx = a.idx;
@@ -629,7 +666,8 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
     o.H = a.H;
     o.G1 = a.G1;
     o.G2 = a.G2;
-    o.R = a.out;
+    o.H2 = a.H2;
+    o.R = OP == OP_FUSED1S ? a.values : a.out;
     o.r = r;
     o.beta = a.beta;
     process_line<OP, TH, TG1, TG2, Acc, L, NV, VW, U, 1>(o, lane, 0, line, begin, end, dst,

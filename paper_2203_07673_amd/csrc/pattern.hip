@@ -210,6 +210,16 @@ __global__ __launch_bounds__(256) void validate_idx_kernel(int32_t nmajor, int32
     else if (p > ptr[lo] && idx[p - 1] >= j) atomicOr(flag, 2);
 }
 
+// ------------------------------------------------------------------ value permutation
+
+template <class T>
+__global__ __launch_bounds__(256) void gather_values_kernel(const int32_t *__restrict__ perm, const T *__restrict__ src,
+                                                            T *__restrict__ dst, int32_t nnz)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < nnz) dst[q] = src[perm[q]];
+}
+
 // ------------------------------------------------------------------ line order
 
 constexpr int32_t kOrderCap = 1023;   // lengths at or above this sort as equal
@@ -413,6 +423,19 @@ hipError_t validate(int32_t nmajor, int32_t nminor, int32_t nnz, const int32_t *
     if (f != 0 || nnz == 0) return hipSuccess;  // bad ptr: idx pass would search a broken ptr
     hipLaunchKernelGGL(validate_idx_kernel, dim3((unsigned)(((int64_t)nnz + 255) / 256)), dim3(256), 0, s, nmajor, nminor,
                        nnz, ptr, idx, flag_dev);
+    return hipGetLastError();
+}
+
+hipError_t gather_values(const int32_t *perm, const void *src, void *dst, int32_t nnz, int val_bytes, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(((int64_t)nnz + 255) / 256));
+    if (val_bytes == 8)
+        hipLaunchKernelGGL(gather_values_kernel<double>, grid, dim3(256), 0, s, perm, static_cast<const double *>(src),
+                           static_cast<double *>(dst), nnz);
+    else
+        hipLaunchKernelGGL(gather_values_kernel<float>, grid, dim3(256), 0, s, perm, static_cast<const float *>(src),
+                           static_cast<float *>(dst), nnz);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ float64.  Gradients flow to A, B (and to w for the SpMMs); S's values are consta
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 from typing import Optional
 
@@ -193,6 +194,25 @@ class Pattern:
             keep = self.csc.variant
             self.csc = self._desc(C.FMM_CSC)
             self.csc.variant = keep
+
+    def with_values(self, s: torch.Tensor) -> "Pattern":
+        """The same pattern with stored values s (nnz, CSR order, the pattern's value
+        dtype): shares every index array, schedule, order and tuning; the CSC-order
+        copy of s comes from the library's gather through perm."""
+        if not isinstance(s, torch.Tensor) or s.dim() != 1 or s.numel() != self.nnz:
+            raise ValueError(f"values must be a 1-D tensor of nnz = {self.nnz} entries")
+        if s.dtype != self.val_dtype or s.device != self.device:
+            raise TypeError(f"values must be {self.val_dtype} on {self.device}")
+        Q = copy.copy(self)
+        Q.val = s.detach().contiguous()
+        Q.valT = torch.empty(max(1, self.nnz), dtype=self.val_dtype, device=self.device)
+        vcode = C.FMM_F64 if self.val_dtype == torch.float64 else C.FMM_F32
+        C.call("fmm_gather_values", _ptr(self.perm), _ptr(Q.val), vcode, _ptr(Q.valT), self.nnz, _stream())
+        Q.csr = Q._desc(C.FMM_CSR)
+        Q.csr.variant = self.csr.variant
+        Q.csc = Q._desc(C.FMM_CSC)
+        Q.csc.variant = self.csc.variant
+        return Q
 
     def set_line_order(self, orient, enabled: bool):
         """Process one orientation's lines by decreasing length (True) or in index order."""
@@ -443,6 +463,38 @@ def fusedmm_b_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fus
     return dA, dB
 
 
+
+def fusedmm_a_backward_values_raw(P, A, B, dC, dS=None, dA=None, want_dA=False, fused=True):
+    """dL/dS at S's stored entries (CSR order) for C = FusedMMA(S, A, B):
+    dS_ij = <A_i, B_j> <dC_i, B_j>; with want_dA the same fused pass also gives dA."""
+    r = A.shape[1]
+    dcode, odt = _common(P, A, B)
+    _check_dense("dC", dC, P.m, r, P.device)
+    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else dS
+    if want_dA and dA is None:
+        dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A_BWD_VALUES, r, dcode)
+    C.call("fmm_fusedmm_a_backward_values", ctypes.byref(P.csr), _ptr(A), _ptr(B), _ptr(dC), r, dcode, _ptr(dS),
+           _ptr(dA if want_dA else None), C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(ws), wb, _stream())
+    return dS[:P.nnz], (dA if want_dA else None)
+
+
+def fusedmm_b_backward_values_raw(P, A, B, dC, dS=None, dB=None, want_dB=False, fused=True):
+    """dL/dS (CSR order) for C' = FusedMMB(S, A, B): dS_ij = <A_i, B_j> <A_i, dC_j>; with
+    want_dB the same fused pass (on the transposed copy) also gives dB."""
+    r = A.shape[1]
+    dcode, odt = _common(P, A, B)
+    _check_dense("dC", dC, P.n, r, P.device)
+    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else dS
+    if want_dB and dB is None:
+        dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B_BWD_VALUES, r, dcode)
+    C.call("fmm_fusedmm_b_backward_values", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
+           dcode, _ptr(dS), _ptr(dB if want_dB else None), C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(ws), wb,
+           _stream())
+    return dS[:P.nnz], (dB if want_dB else None)
+
+
 def sddmm_raw(P, A, B, out=None, orient=C.FMM_CSR, beta=0.0):
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
@@ -514,6 +566,44 @@ class _FusedMMB(torch.autograd.Function):
         return None, dA, dB, None
 
 
+class _FusedMMValues(torch.autograd.Function):
+    """FusedMMA / FusedMMB with S's stored values s as a differentiable input."""
+
+    @staticmethod
+    def forward(ctx, P, A, B, s, form, fused):
+        Q = P.with_values(s)
+        raw = fusedmm_a_raw if form == "a" else fusedmm_b_raw
+        C_out, R_ws = raw(Q, A, B, fused=fused)
+        ctx.Q, ctx.form, ctx.fused, ctx.R = Q, form, fused, R_ws
+        ctx.save_for_backward(A, B)
+        return C_out
+
+    @staticmethod
+    def backward(ctx, dC):
+        A, B = ctx.saved_tensors
+        Q, form, fused = ctx.Q, ctx.form, ctx.fused
+        dC = dC.contiguous()
+        needA, needB, needS = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[3]
+        dA = dB = ds = None
+        if form == "a":
+            if needS:  # the fused pass that writes dS also writes dA
+                ds, dA = fusedmm_a_backward_values_raw(Q, A, B, dC, want_dA=needA and fused, fused=fused)
+            rest = (needA and dA is None, needB)
+            if any(rest):
+                xA, xB = fusedmm_a_backward_raw(Q, A, B, dC, need=rest, fused=fused, R_ws=ctx.R)
+                dA = xA if rest[0] else dA
+                dB = xB
+        else:
+            if needS:
+                ds, dB = fusedmm_b_backward_values_raw(Q, A, B, dC, want_dB=needB and fused, fused=fused)
+            rest = (needA, needB and dB is None)
+            if any(rest):
+                xA, xB = fusedmm_b_backward_raw(Q, A, B, dC, need=rest, fused=fused, R_ws=ctx.R)
+                dA = xA
+                dB = xB if rest[1] else dB
+        return None, dA, dB, ds, None, None
+
+
 class _SDDMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P, A, B):
@@ -580,13 +670,19 @@ class _SpMMB(torch.autograd.Function):
         return None, dA, (dw[:P.nnz] if dw is not None else None)
 
 
-def fusedmm_a(P: Pattern, A, B, fused: bool = True):
-    """FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B), differentiable in A and B."""
+def fusedmm_a(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None):
+    """FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B), differentiable in A and B, and in
+    S's stored values when they are given as ``values`` (nnz, CSR order)."""
+    if values is not None:
+        return _FusedMMValues.apply(P, A, B, values, "a", fused)
     return _FusedMMA.apply(P, A, B, fused)
 
 
-def fusedmm_b(P: Pattern, A, B, fused: bool = True):
-    """FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A), differentiable in A and B."""
+def fusedmm_b(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None):
+    """FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A), differentiable in A and B, and in
+    S's stored values when they are given as ``values``."""
+    if values is not None:
+        return _FusedMMValues.apply(P, A, B, values, "b", fused)
     return _FusedMMB.apply(P, A, B, fused)
 
 

@@ -178,3 +178,27 @@ def test_line_order_argument_errors():
     assert lib.fmm_line_order(FAKE, 100000, 8, FAKE, FAKE, need - 1, None) == -7  # workspace too small
     assert lib.fmm_line_order(FAKE, 100000, 8, FAKE, FAKE + 4, need, None) == -7  # misaligned workspace
     assert lib.fmm_line_order(None, 0, 8, None, None, 0, None) == 0              # nothing to order
+
+
+def test_value_gradient_argument_errors():
+    lib = C.load()
+    d = _desc()
+    assert lib.fmm_fusedmm_a_backward_values(None, FAKE, FAKE, FAKE, 32, 0, FAKE, None, 0, None, 0, None) == -1
+    assert lib.fmm_fusedmm_a_backward_values(ctypes.byref(_desc(orient=C.FMM_CSC)), FAKE, FAKE, FAKE, 32, 0, FAKE,
+                                             None, 0, None, 0, None) == -4
+    assert lib.fmm_fusedmm_a_backward_values(ctypes.byref(d), FAKE, FAKE, FAKE, 32, 0, None, None, 0, None, 0,
+                                             None) == -1                                     # dS required
+    assert lib.fmm_fusedmm_a_backward_values(ctypes.byref(d), FAKE, FAKE, FAKE, 32, 0, FAKE, None, 3, None, 0,
+                                             None) == -2                                     # bad flags
+    assert lib.fmm_fusedmm_a_backward_values(ctypes.byref(d), FAKE, FAKE, FAKE, 32, 0, FAKE, FAKE, 1, None, 0,
+                                             None) == -8                                     # unfused: no dA
+    assert lib.fmm_fusedmm_a_backward_values(ctypes.byref(d), FAKE, FAKE, FAKE, 12, 1, FAKE, None, 0, None, 0,
+                                             None) == -3                                     # bf16 needs r % 8
+    dc = _desc(orient=C.FMM_CSC)
+    dc.perm = None
+    assert lib.fmm_fusedmm_b_backward_values(ctypes.byref(d), ctypes.byref(dc), FAKE, FAKE, FAKE, 32, 0, FAKE, None,
+                                             0, None, 0, None) == -1                         # fused needs perm
+    assert lib.fmm_gather_values(FAKE, FAKE, 1, FAKE, 10, None) == -3                        # values are f32/f64
+    assert lib.fmm_gather_values(None, FAKE, 0, FAKE, 10, None) == -1
+    assert lib.fmm_gather_values(FAKE, FAKE, 0, FAKE, -1, None) == -2
+    assert lib.fmm_gather_values(None, None, 0, None, 0, None) == 0
