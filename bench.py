@@ -683,6 +683,39 @@ def main():
         variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
         variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
         del A16, B16
+        # learned edge values: the adjoint also returns dL/dS; fused, dS is written by the
+        # row pass that computes dA, unfused it costs two SDDMM passes on top
+        Q = P.with_values(P.val.clone())
+        dS = torch.empty(nnz, dtype=torch.float32, device=dev)
+
+        def make_values_step(fused, R_ws=None, dP_ws=None):
+            def step(ev=None):
+                if ev is not None:
+                    ev[0].record()
+                F.fusedmm_a_raw(Q, A, B, out=C, fused=fused, R_ws=R_ws)
+                if ev is not None:
+                    ev[1].record()
+                F.fusedmm_a_backward_values_raw(Q, A, B, G, dS=dS, dA=dA, want_dA=fused, fused=fused)
+                if not fused:
+                    F.fusedmm_a_backward_raw(Q, A, B, G, dA=dA, need=(True, False), fused=False, R_ws=R_ws,
+                                             dP_ws=dP_ws)
+                if ev is not None:
+                    ev[2].record()
+                F.fusedmm_a_backward_raw(Q, A, B, G, dB=dB, need=(False, True), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
+                if ev is not None:
+                    ev[3].record()
+            return step
+        t_lv, kt_lv = time_steps(make_values_step(True), vsteps, 2)
+        R_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        dP_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
+        t_lvu, kt_lvu = time_steps(make_values_step(False, R_ws, dP_ws), vsteps, 2)
+        del R_ws, dP_ws, Q, dS
+        names = {"fwd": "fwd", "bwd_row": "dS_and_dA", "bwd_col": "dB"}
+        variants["learned_values_fused_f32"] = {"ms_per_step": round(t_lv * 1e3, 4),
+                                                "kernel_ms": {names[k]: round(v, 4) for k, v in kt_lv.items()}}
+        variants["learned_values_unfused_f32"] = {"ms_per_step": round(t_lvu * 1e3, 4),
+                                                  "kernel_ms": {names[k]: round(v, 4) for k, v in kt_lvu.items()}}
+        log(f"learned values step: fused {t_lv * 1e3:.3f} ms, unfused {t_lvu * 1e3:.3f} ms")
         # FusedMMB forward, fused and unfused
         Cb = torch.empty(n, r, dtype=torch.float32, device=dev)
         Rb = torch.empty(nnz, dtype=torch.float32, device=dev)
