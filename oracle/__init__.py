@@ -344,6 +344,50 @@ def gat_forward(S, H, a1, a2, slope=0.2, softmax=True, use_val=True, rows=None):
 # Alternating least squares (Section VI-E): batched CG on the per-line normal equations
 # ----------------------------------------------------------------------------------
 
+
+def gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True, use_val=True):
+    """Adjoint of the attention head out = W H (the paper gives the forward only; this is
+    the chain rule through its definition, step by step).  With upstream gradient dO:
+
+      x_ij = S_ij (s_i + t_j), e = LeakyReLU(x), w = e or its row softmax,
+      dw_ij = <dO_i, H_j>                                 (an SDDMM on the pattern)
+      de_ij = dw_ij, or with the softmax  w_ij (dw_ij - sum_k w_ik dw_ik)
+      dx_ij = de_ij * (1 if x_ij > 0 else slope)          (LeakyReLU's derivative)
+      dS_ij = dx_ij (s_i + t_j);   ds_i = sum_j dx_ij S_ij;   dt_j = sum_i dx_ij S_ij
+      dH    = W^T dO + ds a1^T + dt a2^T;   da1 = H^T ds;   da2 = H^T dt
+
+    Returns (dH, da1, da2, dS); dS is None without stored values (use_val False)."""
+    H, dO = _f64(H), _f64(dO)
+    a1, a2 = _f64(a1), _f64(a2)
+    n = H.shape[0]
+    s, t = gat_scores(H, a1, a2)
+    rows = np.repeat(np.arange(S.m), np.diff(np.asarray(S.rowptr, np.int64)))
+    cols = np.asarray(S.colidx, np.int64)
+    v = _f64(S.val) if use_val and S.val is not None else np.ones(cols.shape[0])
+    score = s[rows] + t[cols]
+    x = v * score
+    w = gat_edges(S, s, t, slope, softmax, use_val)
+    dw = sddmm(S, dO, H, val=None)
+    if softmax:
+        D = np.zeros(S.m)
+        for p in range(cols.shape[0]):  # row sums in stored order
+            D[rows[p]] += w[p] * dw[p]
+        de = w * (dw - D[rows])
+    else:
+        de = dw
+    dx = de * np.where(x > 0, 1.0, slope)
+    g = dx * v
+    ds = np.zeros(n)
+    dt = np.zeros(n)
+    for p in range(cols.shape[0]):
+        ds[rows[p]] += g[p]
+        dt[cols[p]] += g[p]
+    dH = spmm_b(S, w, dO) + np.outer(ds, a1) + np.outer(dt, a2)
+    da1 = H.T @ ds
+    da2 = H.T @ dt
+    dS = dx * score if use_val and S.val is not None else None
+    return dH, da1, da2, dS
+
 def gram_apply(S, X, F):
     """Per line i of S's pattern: sum_j <X_i, F_j> F_j (S's values ignored)."""
     return spmm_a(S, sddmm(S, X, F, val=None), F)

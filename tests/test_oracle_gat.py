@@ -83,3 +83,83 @@ def test_gat_single_neighbour_copies_row_and_weights_sum_to_one():
     w = oracle.gat_edges(S2, s, t, softmax=True)
     sums = np.add.reduceat(w, S2.rowptr[:-1][np.diff(S2.rowptr) > 0])
     assert np.allclose(sums, 1.0, atol=1e-14, rtol=0)
+
+
+# ------------------------------------------------------------ adjoint of the attention head
+
+def _torch_head(S, H, a1, a2, vals, slope, softmax):
+    """The head through torch on the dense masked matrix (autograd reference)."""
+    rows = torch.tensor(np.repeat(np.arange(S.m), np.diff(S.rowptr)))
+    cols = torch.tensor(S.colidx.astype(np.int64))
+    M = torch.zeros(S.m, S.n, dtype=torch.bool)
+    M[rows, cols] = True
+    D = torch.zeros(S.m, S.n, dtype=torch.float64).index_put((rows, cols), vals)
+    s, t = H @ a1, H @ a2
+    E = torch.nn.functional.leaky_relu(D * (s[:, None] + t[None, :]), negative_slope=slope)
+    if softmax:
+        W = torch.nan_to_num(torch.softmax(E.masked_fill(~M, float("-inf")), dim=1), nan=0.0)
+    else:
+        W = E * M
+    return W @ H
+
+
+@pytest.mark.parametrize("softmax", [True, False])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gat_backward_vs_torch_autograd(softmax, seed):
+    case = tiny_case(19, 19, 6, 0.35, seed=320 + seed)
+    S, H = case["S"], case["A"]
+    rng = np.random.default_rng(330 + seed)
+    a1, a2 = rng.standard_normal(6), rng.standard_normal(6)
+    dO = rng.standard_normal((19, 6))
+    Ht = torch.tensor(H, requires_grad=True)
+    a1t, a2t = torch.tensor(a1, requires_grad=True), torch.tensor(a2, requires_grad=True)
+    vt = torch.tensor(np.asarray(S.val, np.float64), requires_grad=True)
+    (_torch_head(S, Ht, a1t, a2t, vt, 0.2, softmax) * torch.tensor(dO)).sum().backward()
+    dH, da1, da2, dS = oracle.gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=softmax)
+    for got, ref in ((dH, Ht.grad), (da1, a1t.grad), (da2, a2t.grad), (dS, vt.grad)):
+        ref = ref.numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-11 * (1 + np.abs(ref).max())
+
+
+def test_gat_backward_central_differences():
+    S = er_exact_degree(40, 40, 5, seed=340, val_dtype=np.float64)
+    rng = np.random.default_rng(341)
+    H = rng.standard_normal((40, 4))
+    a1, a2 = rng.standard_normal(4) * 0.5, rng.standard_normal(4) * 0.5
+    dO = rng.standard_normal((40, 4))
+    dH, da1, da2, dS = oracle.gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True)
+
+    def loss():
+        return float((oracle.gat_forward(S, H, a1, a2, slope=0.2, softmax=True) * dO).sum())
+
+    h = 1e-6
+    for X, dX in ((H, dH), (a1, da1), (a2, da2), (S.val, dS)):
+        flat = X.reshape(-1)
+        for k in rng.choice(flat.size, min(40, flat.size), replace=False):
+            old = flat[k]
+            flat[k] = old + h
+            lp = loss()
+            flat[k] = old - h
+            lm = loss()
+            flat[k] = old
+            assert abs((lp - lm) / (2 * h) - dX.reshape(-1)[k]) <= 1e-6 * max(1.0, abs(dX.reshape(-1)[k]))
+
+
+def test_gat_backward_softmax_rows_are_shift_invariant():
+    """With the softmax and every stored value 1, a row's scores all carry the same s_i,
+    which the softmax cancels while LeakyReLU stays on one branch: the output does not
+    depend on s, so the gradient through it vanishes (da1 = 0 up to rounding).  Positive
+    H and a2 shifted down keep every x_ij = s_i + t_j negative, with t still spread."""
+    S = rmat(7, 6, seed=350)
+    S1 = type(S)(S.m, S.n, S.rowptr, S.colidx, np.ones(S.nnz))
+    rng = np.random.default_rng(351)
+    H = rng.random((S.n, 5)) + 0.1
+    a1 = 0.02 * rng.standard_normal(5)
+    a2 = 0.02 * rng.standard_normal(5) - 1.5
+    s, t = H @ a1, H @ a2
+    rows = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    assert np.all(s[rows] + t[S.colidx] < 0) and np.ptp(t) > 1.0
+    dO = rng.standard_normal((S.m, 5))
+    _, da1, da2, _ = oracle.gat_backward(S1, H, a1, a2, dO, slope=0.2, softmax=True)
+    assert np.max(np.abs(da1)) <= 1e-12 * (1 + np.abs(da2).max() + np.abs(H).sum())
+    assert np.max(np.abs(da2)) > 1e-3
