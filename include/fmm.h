@@ -421,6 +421,30 @@ fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, co
 fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t, int32_t dtype,
                                double negative_slope, int32_t flags, void *w, hipStream_t stream);
 
+/*
+ * Adjoint of the attention head (the paper evaluates the forward only; this is the chain
+ * rule through the definition above).  Given the forward's s, t (fmm_gat_scores) and
+ * out (fmm_gat_forward with the same flags and slope), and the upstream gradient dO:
+ *
+ *   dw_ij = <dO_i, H_j>;  de = dw, or with the softmax w_ij (dw_ij - <dO_i, out_i>)
+ *   dx_ij = de_ij * (1 if S_ij (s_i + t_j) > 0 else negative_slope)
+ *   dS_ij = dx_ij (s_i + t_j)   (CSR order; skipped when dS is NULL)
+ *   ds_i = sum_j dx_ij S_ij,  dt_j = sum_i dx_ij S_ij
+ *   dH = W^T dO + ds a1^T + dt a2^T,  da1 = H^T ds,  da2 = H^T dt
+ *
+ * Two passes over the pattern (rows on S_csr, columns on S_csc), each recomputing the
+ * edge weights and dw in registers; no atomics, fixed summation orders.  Both
+ * descriptors' split schedules and orders are honoured.  dtype as for fmm_gat_forward
+ * (dO, out, dH, da1, da2, s, t, a1, a2 float32; float64 for FMM_F64).  ws: a device
+ * workspace of fmm_gat_backward_workspace() bytes, 256-byte aligned.
+ */
+fmm_status fmm_gat_backward_workspace(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, int32_t dtype,
+                                      size_t *bytes);
+fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *H, const void *a1,
+                            const void *a2, const void *s, const void *t, const void *out, const void *dO, int32_t r,
+                            int32_t dtype, double negative_slope, int32_t flags, void *dH, void *da1, void *da2,
+                            void *dS, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- alternating least squares */
 
 /*

@@ -20,6 +20,8 @@ from .fusedmm import (  # noqa: F401
     fusedmm_b_backward_raw,
     fusedmm_b_backward_values_raw,
     fusedmm_b_raw,
+    gat,
+    gat_backward,
     gat_edge_values,
     gat_forward,
     gat_forward_unfused,

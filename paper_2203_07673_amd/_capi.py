@@ -105,6 +105,8 @@ SIGNATURES = {
     "fmm_csr_to_csc_workspace": [_I32, _I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_csr_to_csc": [_I32, _I32, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P],
     "fmm_gather_values": [_P, _P, _I32, _P, _I32, _P],
+    "fmm_gat_backward_workspace": [_SP, _SP, _I32, _I32, ctypes.POINTER(_SZ)],
+    "fmm_gat_backward": [_SP, _SP, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P],
     "fmm_fusedmm_a_backward_values": [_SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
     "fmm_fusedmm_b_backward_values": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
     "fmm_line_order_workspace": [_I32, ctypes.POINTER(_SZ)],

@@ -25,7 +25,7 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "cg_lines", "als_residual",
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "gat_backward", "gat", "cg_lines", "als_residual",
            "als_sweep"]
 
 DEFAULT_LONG_LEN = 128
@@ -736,6 +736,57 @@ def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=Non
     C.call("fmm_gat_forward", ctypes.byref(P.csr), _ptr(s), _ptr(t), _ptr(H), r, dcode, float(negative_slope),
            C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(ws), nb.value, _stream())
     return out
+
+
+def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=True, want_dS=False):
+    """Adjoint of gat_forward: (dH, da1, da2, dS) for upstream gradient dO, from the
+    forward's output ``out`` (dS, the gradient for S's stored values in CSR order, only
+    with want_dS)."""
+    r = H.shape[1]
+    _check_dense("H", H, P.n, r, P.device)
+    dcode, odt = _common(P, H, None)
+    _check_dense("out", out, P.m, r, P.device)
+    dO = dO.contiguous()
+    _check_dense("dO", dO, P.m, r, P.device)
+    s, t = gat_scores(H, a1, a2)
+    dH = torch.empty(P.n, r, dtype=odt, device=P.device)
+    da1 = torch.empty(r, dtype=odt, device=P.device)
+    da2 = torch.empty(r, dtype=odt, device=P.device)
+    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if want_dS else None
+    nb = ctypes.c_size_t(0)
+    C.call("fmm_gat_backward_workspace", ctypes.byref(P.csr), ctypes.byref(P.csc), r, dcode, ctypes.byref(nb))
+    ws = P._ws_cache.get(("gat_bwd", nb.value))
+    if ws is None:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
+        P._ws_cache[("gat_bwd", nb.value)] = ws
+    C.call("fmm_gat_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(H), _ptr(a1.contiguous()),
+           _ptr(a2.contiguous()), _ptr(s), _ptr(t), _ptr(out), _ptr(dO), r, dcode, float(negative_slope),
+           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(dH), _ptr(da1), _ptr(da2), _ptr(dS), _ptr(ws), nb.value,
+           _stream())
+    return dH, da1, da2, (dS[:P.nnz] if want_dS else None)
+
+
+class _GAT(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, H, a1, a2, values, negative_slope, softmax):
+        Q = P.with_values(values) if values is not None else P
+        out = gat_forward(Q, H, a1, a2, negative_slope=negative_slope, softmax=softmax)
+        ctx.Q, ctx.slope, ctx.softmax = Q, negative_slope, softmax
+        ctx.save_for_backward(H, a1, a2, out)
+        return out
+
+    @staticmethod
+    def backward(ctx, dO):
+        H, a1, a2, out = ctx.saved_tensors
+        want_dS = ctx.needs_input_grad[4]
+        dH, da1, da2, dS = gat_backward(ctx.Q, H, a1, a2, out, dO, ctx.slope, ctx.softmax, want_dS=want_dS)
+        return None, dH, da1, da2, dS, None, None
+
+
+def gat(P: Pattern, H, a1, a2, values=None, negative_slope=0.2, softmax=True):
+    """The attention head as a differentiable function of H, a1, a2 and, when given,
+    S's stored values (learned edge values, nnz in CSR order)."""
+    return _GAT.apply(P, H, a1, a2, values, negative_slope, softmax)
 
 
 def cg_lines(P: Pattern, orient, F, rhs, lam, iters, X):

@@ -7,7 +7,7 @@ import oracle
 import paper_2203_07673_amd as F
 from tests.gates import TOL_BF16, TOL_F32, TOL_F64
 from tests.gpu_helpers import dev, gate, host, log
-from workloads import CsrPattern, dense_normal, er_exact_degree, rmat, workload
+from workloads import CsrPattern, dense_normal, er_exact_degree, rmat, tiny_case, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -145,3 +145,81 @@ def test_gat_edge_values_and_unfused_head(softmax):
     out = host(F.gat_forward_unfused(P, dev(H), dev(a1), dev(a2), softmax=softmax))
     ref, mg = _ref(S, H, a1, a2, 0.2, softmax)
     gate(f"unfused head softmax={softmax}", out, ref, mg, TOL_F32)
+
+
+# ------------------------------------------------------------ adjoint of the attention head
+
+def _gate_max(name, got, ref, tol):
+    """Max-norm relative gate: max |got - ref| <= tol * max |ref|.  The adjoint's outputs
+    are sums of signed terms (the softmax's w (dw - D), ds and dt over a row or column),
+    so a per-element companion would need an error analysis of exp and of D; the
+    max-norm form bounds the error against the output's scale instead."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    scale = max(np.abs(ref).max() if ref.size else 0.0, 1e-300)
+    err = np.abs(got - ref).max() / scale if ref.size else 0.0
+    assert err <= tol, f"{name}: max-norm relative error {err:.3e} > {tol:.1e}"
+
+
+BWD_CASES = [
+    ("er_r64", lambda: er_exact_degree(700, 700, 12, seed=601), 64, False),
+    ("rmat_r128_split", lambda: rmat(11, 8, seed=602), 128, True),
+    ("rmat_r8_split", lambda: rmat(10, 16, seed=603), 8, True),
+    ("er_r3", lambda: er_exact_degree(300, 300, 9, seed=604), 3, False),
+]
+
+
+@pytest.mark.parametrize("case", [c[0] for c in BWD_CASES])
+def test_gat_backward_parity(case):
+    _, build, r, split = [c for c in BWD_CASES if c[0] == case][0]
+    S32 = build()
+    for dtype in (torch.float32, torch.float64, torch.bfloat16):
+        if dtype == torch.bfloat16 and r % 8:
+            continue
+        npdt = np.float64 if dtype == torch.float64 else np.float32
+        S = S32 if dtype != torch.float64 else CsrPattern(S32.m, S32.n, S32.rowptr, S32.colidx,
+                                                            S32.val.astype(np.float64))
+        H = dense_normal(S.n, r, 610, dtype=npdt)
+        a1 = dense_normal(1, r, 611, sigma=r ** -0.5, dtype=npdt)[0]
+        a2 = dense_normal(1, r, 612, sigma=r ** -0.5, dtype=npdt)[0]
+        dO = dense_normal(S.m, r, 613, dtype=npdt)
+        odt = torch.float64 if dtype == torch.float64 else torch.float32
+        P = F.Pattern.from_csr(S, long_len=64 if split else 1 << 30, chunk=32 if split else 1 << 30, split=split)
+        Hd = F.to_bf16(dev(H)) if dtype == torch.bfloat16 else dev(H, dtype)
+        Hq = oracle.bf16_round(H) if dtype == torch.bfloat16 else H
+        tol = TOL_F64 if dtype == torch.float64 else TOL_F32
+        for softmax in (True, False):
+            log(f"gat backward {case} {dtype} softmax={softmax}")
+            a1d, a2d = dev(a1, odt), dev(a2, odt)
+            out = F.gat_forward(P, Hd, a1d, a2d, softmax=softmax)
+            dH, da1, da2, dS = F.gat_backward(P, Hd, a1d, a2d, out, dev(dO, odt), softmax=softmax, want_dS=True)
+            # the oracle on the same (rounded, for bf16) features isolates accumulation error
+            ref = oracle.gat_backward(S, Hq, a1, a2, dO, slope=0.2, softmax=softmax)
+            for name, got, want in zip(("dH", "da1", "da2", "dS"), (dH, da1, da2, dS), ref):
+                _gate_max(f"{case} {dtype} softmax={softmax} {name}", host(got), want, tol)
+
+
+@pytest.mark.parametrize("softmax", [True, False])
+def test_gat_autograd_and_gradcheck(softmax):
+    S = rmat(9, 8, seed=620)
+    r = 16
+    H = dense_normal(S.n, r, 621)
+    a1 = dense_normal(1, r, 622, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 623, sigma=r ** -0.5)[0]
+    G = dense_normal(S.m, r, 624)
+    log(f"gat autograd softmax={softmax}")
+    P = F.Pattern.from_csr(S, long_len=32, chunk=16)
+    Ht, a1t, a2t = dev(H).requires_grad_(True), dev(a1).requires_grad_(True), dev(a2).requires_grad_(True)
+    vt = dev(S.val).requires_grad_(True)
+    out = F.gat(P, Ht, a1t, a2t, values=vt, softmax=softmax)
+    (out * dev(G)).sum().backward()
+    ref = oracle.gat_backward(S, H, a1, a2, G, slope=0.2, softmax=softmax)
+    for name, got, want in zip(("dH", "da1", "da2", "dS"), (Ht.grad, a1t.grad, a2t.grad, vt.grad), ref):
+        _gate_max(f"autograd {name}", host(got), want, TOL_F32)
+    small = tiny_case(14, 14, 3, 0.35, seed=625)
+    Ss = small["S"]
+    Ps = F.Pattern.from_csr(Ss, val_dtype=torch.float64)
+    args = (dev(small["A"]).requires_grad_(True), dev(np.array([0.3, -0.2, 0.5])).requires_grad_(True),
+            dev(np.array([-0.4, 0.1, 0.2])).requires_grad_(True),
+            dev(np.asarray(Ss.val, np.float64)).requires_grad_(True))
+    assert torch.autograd.gradcheck(lambda h, x, y, v: F.gat(Ps, h, x, y, values=v, softmax=softmax), args,
+                                    eps=1e-6, atol=1e-8)
