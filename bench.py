@@ -366,9 +366,9 @@ def run_batch(args):
 
 
 def run_gat(args):
-    """Graph-attention forward (Section VI-E): 4 heads of r = 128 on the R-MAT scale 20
-    graph, softmax-normalised; fused one-pass head vs the unfused sequence (edge values
-    written to memory, then an SpMM)."""
+    """Graph-attention head (Section VI-E): 4 heads of r = 128 on the R-MAT scale 20
+    graph, softmax-normalised; fused one-pass forward vs the unfused sequence (edge values
+    written to memory, then an SpMM), and the adjoint of every head."""
     import torch
 
     import paper_2203_07673_amd as F
@@ -408,6 +408,23 @@ def run_gat(args):
             F.gat_forward_unfused(P, Hl[h], a[h][0], a[h][1], softmax=True, out=outs[h])
 
     tu = timeit(lambda: step_unfused(Hs), args.steps, args.warmup)
+
+    # adjoint of every head (dH, da1, da2) from the forward outputs and an upstream gradient
+    dOs = [torch.from_numpy(dense_normal(S.m, r, 800 + h)).to(dev) for h in range(heads)]
+
+    lses = [torch.empty(S.m, device=dev) for _ in range(heads)]
+
+    def fwd_lse(Hl):
+        for h in range(heads):
+            F.gat_forward(P, Hl[h], a[h][0], a[h][1], softmax=True, out=outs[h], lse=lses[h])
+
+    def step_bwd(Hl):
+        for h in range(heads):
+            F.gat_backward(P, Hl[h], a[h][0], a[h][1], outs[h], dOs[h], softmax=True, lse=lses[h])
+    fwd_lse(Hs)
+    tb32 = timeit(lambda: step_bwd(Hs), args.steps, args.warmup)
+    fwd_lse(H16)
+    tb16 = timeit(lambda: step_bwd(H16), args.steps, args.warmup)
     # gather model per head: each stored entry fetches its feature row and t_j; rows read H once
     # for the scores and write out once
     nnz, n = S.nnz, S.n
@@ -416,6 +433,8 @@ def run_gat(args):
            "nnz": nnz, "n": n, "r": r, "heads": heads,
            "fused_f32_ms": round(t32 * 1e3, 4), "fused_bf16_ms": round(t16 * 1e3, 4),
            "unfused_f32_ms": round(tu * 1e3, 4), "speedup_fused_f32_vs_unfused_f32": round(tu / t32, 3),
+           "backward_f32_ms": round(tb32 * 1e3, 4), "backward_bf16_ms": round(tb16 * 1e3, 4),
+           "train_step_f32_ms": round((t32 + tb32) * 1e3, 4),
            "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3)}
     print(json.dumps(out), flush=True)
 

@@ -404,14 +404,17 @@ fmm_status fmm_spmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
  * maximum grows).  Rows with no stored entry give 0.  dtype is H's storage (FMM_F32,
  * FMM_BF16, FMM_F64); a1, a2, s, t, out and S's values are float32 (float64 for
  * FMM_F64).  A split schedule on S is honoured; it then needs a workspace of
- * fmm_gat_workspace() bytes.  Multi-head attention is one call per head.
+ * fmm_gat_workspace() bytes.  Multi-head attention is one call per head.  With the
+ * softmax, lse (optional, n values; NULL skips it) receives each row's log-sum-exp
+ * max_k e_ik + log sum_k exp(e_ik - max_k e_ik) (0 for an empty row), which the adjoint
+ * uses to recompute the weights.
  */
 #define FMM_GAT_SOFTMAX 1
 fmm_status fmm_gat_scores(const void *H, int32_t n, int32_t r, int32_t dtype, const void *a1, const void *a2,
                           void *s, void *t, hipStream_t stream);
 fmm_status fmm_gat_workspace(const fmm_sparse *S, int32_t r, int32_t dtype, size_t *bytes);
 fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, const void *H, int32_t r, int32_t dtype,
-                           double negative_slope, int32_t flags, void *out, void *ws, size_t ws_bytes,
+                           double negative_slope, int32_t flags, void *out, void *lse, void *ws, size_t ws_bytes,
                            hipStream_t stream);
 /*
  * The edge values w_ij themselves, in CSR order (nnz values, float32; float64 for
@@ -423,8 +426,9 @@ fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t
 
 /*
  * Adjoint of the attention head (the paper evaluates the forward only; this is the chain
- * rule through the definition above).  Given the forward's s, t (fmm_gat_scores) and
- * out (fmm_gat_forward with the same flags and slope), and the upstream gradient dO:
+ * rule through the definition above).  Given the forward's s, t (fmm_gat_scores), out
+ * and, with the softmax, lse (fmm_gat_forward with the same flags and slope), and the
+ * upstream gradient dO:
  *
  *   dw_ij = <dO_i, H_j>;  de = dw, or with the softmax w_ij (dw_ij - <dO_i, out_i>)
  *   dx_ij = de_ij * (1 if S_ij (s_i + t_j) > 0 else negative_slope)
@@ -441,7 +445,8 @@ fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t
 fmm_status fmm_gat_backward_workspace(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, int32_t dtype,
                                       size_t *bytes);
 fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *H, const void *a1,
-                            const void *a2, const void *s, const void *t, const void *out, const void *dO, int32_t r,
+                            const void *a2, const void *s, const void *t, const void *out, const void *lse,
+                            const void *dO, int32_t r,
                             int32_t dtype, double negative_slope, int32_t flags, void *dH, void *da1, void *da2,
                             void *dS, void *ws, size_t ws_bytes, hipStream_t stream);
 

@@ -106,7 +106,7 @@ SIGNATURES = {
     "fmm_csr_to_csc": [_I32, _I32, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P],
     "fmm_gather_values": [_P, _P, _I32, _P, _I32, _P],
     "fmm_gat_backward_workspace": [_SP, _SP, _I32, _I32, ctypes.POINTER(_SZ)],
-    "fmm_gat_backward": [_SP, _SP, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P],
+    "fmm_gat_backward": [_SP, _SP, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P],
     "fmm_fusedmm_a_backward_values": [_SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
     "fmm_fusedmm_b_backward_values": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _SZ, _P],
     "fmm_line_order_workspace": [_I32, ctypes.POINTER(_SZ)],
@@ -131,7 +131,7 @@ SIGNATURES = {
     "fmm_autotune": [_I32, _SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
     "fmm_gat_scores": [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P],
     "fmm_gat_workspace": [_SP, _I32, _I32, ctypes.POINTER(_SZ)],
-    "fmm_gat_forward": [_SP, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _SZ, _P],
+    "fmm_gat_forward": [_SP, _P, _P, _P, _I32, _I32, _D, _I32, _P, _P, _P, _SZ, _P],
     "fmm_gat_edge_values": [_SP, _P, _P, _I32, _D, _I32, _P, _P],
     "fmm_cg_work_size": [_I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_cg_lines": [_SP, _P, _I32, _I32, _P, ctypes.c_float, _I32, _P, _P, _SZ, _P, _SZ, _P],

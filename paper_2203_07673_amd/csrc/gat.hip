@@ -25,6 +25,9 @@ namespace {
 template <class Acc> __device__ __forceinline__ Acc exp_acc(Acc x);
 template <> __device__ __forceinline__ float exp_acc<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double exp_acc<double>(double x) { return exp(x); }
+template <class Acc> __device__ __forceinline__ Acc log_acc(Acc x);
+template <> __device__ __forceinline__ float log_acc<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double log_acc<double>(double x) { return log(x); }
 template <class Acc> __device__ __forceinline__ Acc neg_inf();
 template <> __device__ __forceinline__ float neg_inf<float>() { return -__builtin_huge_valf(); }
 template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
@@ -114,6 +117,7 @@ struct GatArgs {
     const int32_t *chunks;
     void *partial;  // n_chunks x r sums, then n_chunks x 2 (m, l)
     const int32_t *order;  // row processing order, NULL = index order
+    void *lse;             // softmax: per-row log-sum-exp of the edge values (Acc), or NULL
 };
 
 template <class TH, class Acc, int L, int NV, int VW, int U, bool SOFTMAX>
@@ -243,6 +247,8 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
     } else {
         dst = static_cast<Acc *>(a.out) + (size_t)line * r;
         if (SOFTMAX) inv = l > Acc(0) ? Acc(1) / l : Acc(0);
+        if (SOFTMAX && a.lse && lane == 0)
+            static_cast<Acc *>(a.lse)[line] = l > Acc(0) ? m + log_acc<Acc>(l) : Acc(0);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -259,7 +265,8 @@ __global__ __launch_bounds__(kBlock) void gat_kernel(GatArgs a, int32_t nb_chunk
 template <class Acc, bool SOFTMAX>
 __global__ __launch_bounds__(kBlock) void gat_merge_kernel(const int32_t *__restrict__ splits, int32_t n_splits,
                                                            int32_t r, int32_t n_chunks,
-                                                           const Acc *__restrict__ partial, Acc *__restrict__ out)
+                                                           const Acc *__restrict__ partial, Acc *__restrict__ out,
+                                                           Acc *__restrict__ lse)
 {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (tid >= (int64_t)n_splits * r) return;
@@ -277,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void gat_merge_kernel(const int32_t *__rest
             sum += partial[(size_t)(first + c) * r + k] * f;
         }
         sum = L > Acc(0) ? sum * (Acc(1) / L) : Acc(0);
+        if (lse && k == 0) lse[line] = L > Acc(0) ? M + log_acc<Acc>(L) : Acc(0);
     } else {
         for (int32_t c = 0; c < cnt; ++c) sum += partial[(size_t)(first + c) * r + k];
     }
@@ -405,7 +413,7 @@ fmm_status fmm_gat_scores(const void *H, int32_t n, int32_t r, int32_t dtype, co
 }
 
 fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, const void *H, int32_t r, int32_t dtype,
-                           double negative_slope, int32_t flags, void *out, void *ws, size_t ws_bytes,
+                           double negative_slope, int32_t flags, void *out, void *lse, void *ws, size_t ws_bytes,
                            hipStream_t stream)
 {
     if (!S) return FMM_ERR_NULL;
@@ -436,6 +444,7 @@ fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, co
     a.chunks = S->chunks;
     a.order = S->order;
     a.partial = ws;
+    a.lse = lse;
     const bool softmax = (flags & FMM_GAT_SOFTMAX) != 0;
     const int uc = gat_uclass(S);
     hipError_t e;
@@ -465,17 +474,17 @@ fmm_status fmm_gat_forward(const fmm_sparse *S, const void *s, const void *t, co
         if (dtype == FMM_F64) {
             if (softmax)
                 hipLaunchKernelGGL((gat_merge_kernel<double, true>), dim3(nb), dim3(kBlock), 0, stream, S->splits,
-                                   S->n_splits, r, S->n_chunks, (const double *)ws, (double *)out);
+                                   S->n_splits, r, S->n_chunks, (const double *)ws, (double *)out, (double *)lse);
             else
                 hipLaunchKernelGGL((gat_merge_kernel<double, false>), dim3(nb), dim3(kBlock), 0, stream, S->splits,
-                                   S->n_splits, r, S->n_chunks, (const double *)ws, (double *)out);
+                                   S->n_splits, r, S->n_chunks, (const double *)ws, (double *)out, (double *)lse);
         } else {
             if (softmax)
                 hipLaunchKernelGGL((gat_merge_kernel<float, true>), dim3(nb), dim3(kBlock), 0, stream, S->splits,
-                                   S->n_splits, r, S->n_chunks, (const float *)ws, (float *)out);
+                                   S->n_splits, r, S->n_chunks, (const float *)ws, (float *)out, (float *)lse);
             else
                 hipLaunchKernelGGL((gat_merge_kernel<float, false>), dim3(nb), dim3(kBlock), 0, stream, S->splits,
-                                   S->n_splits, r, S->n_chunks, (const float *)ws, (float *)out);
+                                   S->n_splits, r, S->n_chunks, (const float *)ws, (float *)out, (float *)lse);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hipfail(e);

@@ -9,12 +9,12 @@
 //   dS_ij = dx_ij (s_i + t_j),  ds_i = sum_j dx_ij S_ij,  dt_j = sum_i dx_ij S_ij
 //   dH_j  = sum_i w_ij dO_i + ds_j a1 + dt_j a2,  da1 = H^T ds,  da2 = H^T dt
 //
-// Passes: (1) per row lse_i and D_i from scalars and two contiguous rows; (2) a row pass
-// on S_csr (held dO_i, gathered H_j) for ds and dS; (3) a column pass on the stored
-// transpose (held H_j, gathered dO_i and per-row scalars) for dt and sum_i w_ij dO_i,
-// both recomputing dw in registers like the fused adjoints; (4) chunk merges in chunk
-// order for split lines; (5) dH's rank-one terms with per-block partial sums of da1, da2;
-// (6) those partials summed in block order.  Deterministic throughout: no atomics.
+// Passes: (1) a row pass on S_csr (held dO_i and out_i, gathered H_j) for D_i, ds and dS;
+// (2) a column pass on the stored transpose (held H_j, gathered dO_i and per-row scalars)
+// for dt and dH_j = sum_i w_ij dO_i + ds_j a1 + dt_j a2, both recomputing the edge weight
+// (from the forward's per-row log-sum-exp) and dw in registers like the fused adjoints;
+// (3) chunk merges in chunk order for split lines, then their rank-one terms; (4) per-block
+// partial sums of da1, da2 and (5) their sum in block order.  No atomics anywhere.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -49,7 +49,11 @@ struct GatBwdArgs {
     const int32_t *ptr, *idx;
     const void *val;          // S's values in this orientation (Acc), NULL = 1
     const void *s, *t;        // scores (Acc, per node)
-    const void *lse, *D;      // per row (Acc)
+    const void *lse;          // per row log-sum-exp from the forward (softmax; Acc)
+    void *D;                  // per row <dO_i, out_i> (written by the row pass, read by the column pass)
+    const void *out;          // forward output (row pass)
+    const void *a1, *a2;      // attention vectors (column pass)
+    const void *ds;           // ds from the row pass (column pass)
     const void *held;         // held matrix: dO (row pass, Acc) or H (column pass, TH)
     const void *gath;         // gathered matrix: H (row pass, TH) or dO (column pass, Acc)
     double slope;
@@ -85,59 +89,16 @@ __device__ __forceinline__ bool pick_line(const GatBwdArgs &a, int32_t nb_chunk_
     return !(a.n_chunks > 0 && end - begin > a.long_len);
 }
 
-// (1) lse_i (softmax) and D_i = <dO_i, out_i> for every row.
-template <class Acc, int L, int NV, int VW>
-__global__ __launch_bounds__(kBlock) void gat_bwd_stats_kernel(int32_t n, int32_t r, const int32_t *__restrict__ ptr,
-                                                               const int32_t *__restrict__ idx,
-                                                               const Acc *__restrict__ val, const Acc *__restrict__ s,
-                                                               const Acc *__restrict__ t, Acc slope, int32_t softmax,
-                                                               const Acc *__restrict__ out, const Acc *__restrict__ dO,
-                                                               Acc *__restrict__ lse, Acc *__restrict__ D)
+// Indices and stored values of the batch at p0 (entries past `end` reread the last one).
+template <class Acc, int U>
+__device__ __forceinline__ void load_entries(const int32_t *__restrict__ idx, const Acc *__restrict__ val, int32_t p0,
+                                             int32_t end, int32_t *j, Acc *v)
 {
-    const int lane = threadIdx.x % L;
-    const int64_t row = (int64_t)blockIdx.x * (kBlock / L) + threadIdx.x / L;
-    if (row >= n) return;
-    const int C = r / VW;
-    Acc d = Acc(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const int c = v * L + lane;
-        if (c < C) {
-            Raw<Acc, VW> x, y;
-            x.load(out + row * r + c * VW);
-            y.load(dO + row * r + c * VW);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) d += Acc(x.get(e)) * Acc(y.get(e));
-        }
-    }
-    d = group_sum<L>(d);
-    Acc l_out = Acc(0);
-    if (softmax) {
-        const int32_t b = ptr[row], e = ptr[row + 1];
-        const Acc si = s[row];
-        Acc mx = bneg_inf<Acc>();
-        for (int32_t p = b + lane; p < e; p += L) {
-            const Acc x = (val ? val[p] : Acc(1)) * (si + t[idx[p]]);
-            const Acc v = x >= Acc(0) ? x : slope * x;
-            mx = v > mx ? v : mx;
-        }
-#pragma unroll
-        for (int o = 1; o < L; o <<= 1) {
-            const Acc y = __shfl_xor(mx, o, L);
-            mx = y > mx ? y : mx;
-        }
-        Acc sum = Acc(0);
-        for (int32_t p = b + lane; p < e; p += L) {
-            const Acc x = (val ? val[p] : Acc(1)) * (si + t[idx[p]]);
-            const Acc v = x >= Acc(0) ? x : slope * x;
-            sum += bexp<Acc>(v - mx);
-        }
-        sum = group_sum<L>(sum);
-        l_out = e > b ? mx + blog<Acc>(sum) : Acc(0);
-    }
-    if (lane == 0) {
-        D[row] = d;
-        lse[row] = l_out;
+    for (int u = 0; u < U; ++u) {
+        const int32_t pc = p0 + u < end ? p0 + u : end - 1;
+        j[u] = idx[pc];
+        v[u] = val ? val[pc] : Acc(1);
     }
 }
 
@@ -167,38 +128,47 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
     const TH *H = static_cast<const TH *>(a.gath);
     const Acc *val = static_cast<const Acc *>(a.val);
     const Acc *t = static_cast<const Acc *>(a.t);
+    const Acc *out = static_cast<const Acc *>(a.out);
     const Acc si = static_cast<const Acc *>(a.s)[line];
-    const Acc lse_i = static_cast<const Acc *>(a.lse)[line];
-    const Acc D_i = static_cast<const Acc *>(a.D)[line];
-    const Acc slope = Acc(a.slope);
     const bool softmax = a.softmax != 0;
+    const Acc lse_i = softmax ? static_cast<const Acc *>(a.lse)[line] : Acc(0);
+    const Acc slope = Acc(a.slope);
     Acc *dS = static_cast<Acc *>(a.dS);
     bool act[NV];
     int off[NV];
     Acc hd[E];
+    Acc dd = Acc(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         act[v] = v * L + lane < C;
         off[v] = act[v] ? (v * L + lane) * VW : 0;
-        Raw<Acc, VW> x;
-        if (act[v]) x.load(dO + (size_t)line * r + off[v]);
-        else x.zero();
-#pragma unroll
-        for (int e = 0; e < VW; ++e) hd[v * VW + e] = Acc(x.get(e));
-    }
-    Acc dsum = Acc(0);
-    for (int32_t p0 = begin; p0 < end; p0 += U) {
-        int32_t j[U];
-        bool ok[U];
-        Acc v[U], tj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t p = p0 + u;
-            ok[u] = p < end;
-            const int32_t pc = ok[u] ? p : end - 1;
-            j[u] = a.idx[pc];
-            v[u] = val ? val[pc] : Acc(1);
+        Raw<Acc, VW> x, y;
+        if (act[v]) {
+            x.load(dO + (size_t)line * r + off[v]);
+            y.load(out + (size_t)line * r + off[v]);
+        } else {
+            x.zero();
+            y.zero();
         }
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            hd[v * VW + e] = Acc(x.get(e));
+            dd += Acc(x.get(e)) * Acc(y.get(e));
+        }
+    }
+    // D_i = <dO_i, out_i> (= sum_j w_ij dw_ij); every chunk of a split row writes the same bits
+    const Acc D_i = group_sum<L>(dd);
+    if (lane == 0) static_cast<Acc *>(a.D)[line] = D_i;
+    Acc dsum = Acc(0);
+    // indices and values of the next batch are loaded while this batch's rows arrive
+    int32_t j[U], jn[U];
+    Acc v[U], vn[U];
+    if (begin < end) load_entries<Acc, U>(a.idx, val, begin, end, j, v);
+    for (int32_t p0 = begin; p0 < end; p0 += U) {
+        bool ok[U];
+        Acc tj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = p0 + u < end;
         Raw<TH, VW> g[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -209,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
                 else g[u][q].zero();
             }
         }
+        if (p0 + U < end) load_entries<Acc, U>(a.idx, val, p0 + U, end, jn, vn);
         Acc dw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -227,6 +198,11 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
             entry_grad<Acc>(v[u], score, lse_i, D_i, dw[u], slope, softmax, w, dx);
             dsum += dx * v[u];
             if (dS && lane == (u % L)) dS[p0 + u] = dx * score;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            j[u] = jn[u];
+            v[u] = vn[u];
         }
     }
     if (lane == 0) {
@@ -252,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
     const Acc *s = static_cast<const Acc *>(a.s);
     const Acc *lse = static_cast<const Acc *>(a.lse);
     const Acc *D = static_cast<const Acc *>(a.D);
+    const bool softmax_c = a.softmax != 0;
     const Acc tj = static_cast<const Acc *>(a.t)[line];
     const Acc slope = Acc(a.slope);
     const bool softmax = a.softmax != 0;
@@ -272,23 +249,19 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
         }
     }
     Acc dtsum = Acc(0);
+    int32_t i[U], in_[U];
+    Acc v[U], vn[U];
+    if (begin < end) load_entries<Acc, U>(a.idx, val, begin, end, i, v);
     for (int32_t p0 = begin; p0 < end; p0 += U) {
-        int32_t i[U];
         bool ok[U];
-        Acc v[U], si[U], li[U], Di[U];
+        Acc si[U], li[U], Di[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t p = p0 + u;
-            ok[u] = p < end;
-            const int32_t pc = ok[u] ? p : end - 1;
-            i[u] = a.idx[pc];
-            v[u] = val ? val[pc] : Acc(1);
-        }
+        for (int u = 0; u < U; ++u) ok[u] = p0 + u < end;
         Raw<Acc, VW> g[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             si[u] = s[i[u]];
-            li[u] = lse[i[u]];
+            li[u] = softmax_c ? lse[i[u]] : Acc(0);
             Di[u] = D[i[u]];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
@@ -296,6 +269,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
                 else g[u][q].zero();
             }
         }
+        if (p0 + U < end) load_entries<Acc, U>(a.idx, val, p0 + U, end, in_, vn);
         Acc dw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -317,9 +291,27 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
 #pragma unroll
                 for (int e = 0; e < VW; ++e) acc[q * VW + e] += w * Acc(g[u][q].get(e));
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            i[u] = in_[u];
+            v[u] = vn[u];
+        }
     }
-    Acc *dst = chunk >= 0 ? static_cast<Acc *>(a.part_vec) + (size_t)chunk * r
-                          : static_cast<Acc *>(a.out_vec) + (size_t)line * r;
+    Acc *dst;
+    if (chunk >= 0) {
+        dst = static_cast<Acc *>(a.part_vec) + (size_t)chunk * r;
+    } else {  // a whole column: add the rank-one terms ds_j a1 + dt_j a2 here
+        dst = static_cast<Acc *>(a.out_vec) + (size_t)line * r;
+        const Acc dsj = static_cast<const Acc *>(a.ds)[line];
+        const Acc *a1 = static_cast<const Acc *>(a.a1);
+        const Acc *a2 = static_cast<const Acc *>(a.a2);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (act[v])
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    acc[v * VW + e] += dsj * a1[off[v] + e] + dtsum * a2[off[v] + e];
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         if (act[v]) St<Acc, VW>::run(dst + off[v], acc + v * VW);
@@ -329,35 +321,45 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
     }
 }
 
-// (5) dH_j += ds_j a1 + dt_j a2, and per-block partial sums of ds_j H_j and dt_j H_j over
-// the block's kFinishRows rows (in row order).
+// (3) For the split columns, after their merges: dH_j += ds_j a1 + dt_j a2.
+template <class Acc>
+__global__ __launch_bounds__(kBlock) void gat_bwd_split_finish_kernel(const int32_t *__restrict__ splits,
+                                                                      int32_t n_splits, int32_t r,
+                                                                      const Acc *__restrict__ a1,
+                                                                      const Acc *__restrict__ a2,
+                                                                      const Acc *__restrict__ ds,
+                                                                      const Acc *__restrict__ dt,
+                                                                      Acc *__restrict__ dH)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (tid >= (int64_t)n_splits * r) return;
+    const int32_t line = splits[3 * (tid / r)];
+    const int32_t k = (int32_t)(tid % r);
+    dH[(size_t)line * r + k] += ds[line] * a1[k] + dt[line] * a2[k];
+}
+
+// (4) Per-block partial sums of ds_j H_j and dt_j H_j over the block's kFinishRows rows
+// (in row order).
 template <class TH, class Acc>
-__global__ __launch_bounds__(kBlock) void gat_bwd_finish_kernel(int32_t n, int32_t r, const TH *__restrict__ H,
-                                                                const Acc *__restrict__ a1,
-                                                                const Acc *__restrict__ a2,
-                                                                const Acc *__restrict__ ds,
-                                                                const Acc *__restrict__ dt, Acc *__restrict__ dH,
-                                                                Acc *__restrict__ part)
+__global__ __launch_bounds__(kBlock) void gat_bwd_da_kernel(int32_t n, int32_t r, const TH *__restrict__ H,
+                                                            const Acc *__restrict__ ds, const Acc *__restrict__ dt,
+                                                            Acc *__restrict__ part)
 {
     const int64_t r0 = (int64_t)blockIdx.x * kFinishRows;
     const int64_t r1 = r0 + kFinishRows < n ? r0 + kFinishRows : n;
     for (int k = threadIdx.x; k < r; k += kBlock) {
-        const Acc x1 = a1[k], x2 = a2[k];
         Acc p1 = Acc(0), p2 = Acc(0);
         for (int64_t j = r0; j < r1; ++j) {
-            const Acc dsj = ds[j], dtj = dt[j];
             const Acc h = widen<Acc>(H[j * r + k]);
-            Acc *o = dH + j * r + k;
-            *o = *o + dsj * x1 + dtj * x2;
-            p1 += dsj * h;
-            p2 += dtj * h;
+            p1 += ds[j] * h;
+            p2 += dt[j] * h;
         }
         part[(size_t)blockIdx.x * 2 * r + k] = p1;
         part[(size_t)blockIdx.x * 2 * r + r + k] = p2;
     }
 }
 
-// (6) da1 = sum_b part[b][0:r], da2 = sum_b part[b][r:2r], blocks in order.
+// (5) da1 = sum_b part[b][0:r], da2 = sum_b part[b][r:2r], blocks in order.
 template <class Acc>
 __global__ __launch_bounds__(kBlock) void gat_bwd_reduce_kernel(int32_t nb, int32_t r, const Acc *__restrict__ part,
                                                                 Acc *__restrict__ da1, Acc *__restrict__ da2)
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_reduce_kernel(int32_t nb, int3
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t lse, D, ds, dt, psc_r, pvec_c, psc_c, pblk, total;
+    size_t D, ds, dt, psc_r, pvec_c, psc_c, pblk, total;
 };
 
 BwdLayout bwd_layout(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, size_t ob)
@@ -392,7 +394,6 @@ BwdLayout bwd_layout(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r
     const int64_t nb = (n + kFinishRows - 1) / kFinishRows;
     BwdLayout l;
     size_t o = 0;
-    l.lse = o; o += al256((size_t)n * ob);
     l.D = o; o += al256((size_t)n * ob);
     l.ds = o; o += al256((size_t)n * ob);
     l.dt = o; o += al256((size_t)n * ob);
@@ -413,24 +414,23 @@ Shape bwd_shape(int r, int vw)
 
 template <class TH, class Acc, int L, int NV, int VW>
 hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const TH *H, const Acc *a1, const Acc *a2,
-                         const Acc *s, const Acc *t, const Acc *out, const Acc *dO, int32_t r, Acc slope,
-                         bool softmax, Acc *dH, Acc *da1, Acc *da2, Acc *dS, char *ws, hipStream_t st)
+                         const Acc *s, const Acc *t, const Acc *out, const Acc *lse, const Acc *dO, int32_t r,
+                         Acc slope, bool softmax, Acc *dH, Acc *da1, Acc *da2, Acc *dS, char *ws, hipStream_t st)
 {
     constexpr int GPB = kBlock / L;
-    constexpr int U = 4;
+    constexpr int U = NV == 1 ? 8 : 4;
     const int32_t n = S_csr->rows;
     const BwdLayout lay = bwd_layout(S_csr, S_csc, r, sizeof(Acc));
-    Acc *lse = reinterpret_cast<Acc *>(ws + lay.lse);
     Acc *D = reinterpret_cast<Acc *>(ws + lay.D);
     Acc *ds = reinterpret_cast<Acc *>(ws + lay.ds);
     Acc *dt = reinterpret_cast<Acc *>(ws + lay.dt);
     hipError_t e;
-    if (n == 0) return hipSuccess;
+    if (n == 0) {  // da1 = da2 = 0
+        hipLaunchKernelGGL((gat_bwd_reduce_kernel<Acc>), dim3((unsigned)((2 * r + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, 0, r, (const Acc *)nullptr, da1, da2);
+        return hipGetLastError();
+    }
     const unsigned nb_rows = (unsigned)(((int64_t)n + GPB - 1) / GPB);
-    hipLaunchKernelGGL((gat_bwd_stats_kernel<Acc, L, NV, VW>), dim3(nb_rows), dim3(kBlock), 0, st, n, r, S_csr->ptr,
-                       S_csr->idx, static_cast<const Acc *>(S_csr->val), s, t, slope, (int32_t)softmax, out, dO, lse,
-                       D);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
 
     GatBwdArgs a;
     memset(&a, 0, sizeof(a));
@@ -441,13 +441,14 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.D = D;
     a.slope = (double)slope;
     a.softmax = softmax ? 1 : 0;
-    // (2) row pass
+    // (1) row pass: D, ds, dS
     a.nlines = n;
     a.ptr = S_csr->ptr;
     a.idx = S_csr->idx;
     a.val = S_csr->val;
     a.held = dO;
     a.gath = H;
+    a.out = out;
     a.long_len = S_csr->long_len;
     a.n_chunks = S_csr->n_chunks;
     a.chunks = S_csr->chunks;
@@ -465,13 +466,17 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
                            1, static_cast<const Acc *>(a.part_sc), ds, 0.0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // (3) column pass
+    // (2) column pass: dt and dH (whole columns get their rank-one terms here)
     a.nlines = S_csc->cols;
     a.ptr = S_csc->ptr;
     a.idx = S_csc->idx;
     a.val = S_csc->val;
     a.held = H;
     a.gath = dO;
+    a.out = nullptr;
+    a.a1 = a1;
+    a.a2 = a2;
+    a.ds = ds;
     a.long_len = S_csc->long_len;
     a.n_chunks = S_csc->n_chunks;
     a.chunks = S_csc->chunks;
@@ -485,6 +490,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     hipLaunchKernelGGL((gat_bwd_cols_kernel<TH, Acc, L, NV, VW, U>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
                        0, st, a, (int32_t)nbc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // (3) split columns: merge their chunks, then add their rank-one terms
     if (S_csc->n_chunks > 0 && S_csc->n_splits > 0) {
         const int64_t mv = ((int64_t)S_csc->n_splits * r + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(merge_kernel<Acc>, dim3((unsigned)mv), dim3(kBlock), 0, st, S_csc->splits, S_csc->n_splits,
@@ -494,15 +500,18 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
         hipLaunchKernelGGL(merge_kernel<Acc>, dim3((unsigned)ms), dim3(kBlock), 0, st, S_csc->splits, S_csc->n_splits,
                            1, static_cast<const Acc *>(a.part_sc), dt, 0.0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((gat_bwd_split_finish_kernel<Acc>), dim3((unsigned)mv), dim3(kBlock), 0, st,
+                           S_csc->splits, S_csc->n_splits, r, a1, a2, (const Acc *)ds, (const Acc *)dt, dH);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // (5), (6)
+    // (4), (5) da1 = H^T ds, da2 = H^T dt
     const int64_t nbf = ((int64_t)n + kFinishRows - 1) / kFinishRows;
     Acc *part = reinterpret_cast<Acc *>(ws + lay.pblk);
-    hipLaunchKernelGGL((gat_bwd_finish_kernel<TH, Acc>), dim3((unsigned)nbf), dim3(kBlock), 0, st, n, r, H, a1, a2,
-                       ds, dt, dH, part);
+    hipLaunchKernelGGL((gat_bwd_da_kernel<TH, Acc>), dim3((unsigned)nbf), dim3(kBlock), 0, st, n, r, H,
+                       (const Acc *)ds, (const Acc *)dt, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((gat_bwd_reduce_kernel<Acc>), dim3((unsigned)((2 * r + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       st, (int32_t)nbf, r, part, da1, da2);
+                       st, (int32_t)nbf, r, (const Acc *)part, da1, da2);
     return hipGetLastError();
 }
 
@@ -510,7 +519,8 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
 
 template <class TH, class Acc, int VW>
 hipError_t dispatch_bwd(Shape sh, const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *H, const void *a1,
-                        const void *a2, const void *s, const void *t, const void *out, const void *dO, int32_t r,
+                        const void *a2, const void *s, const void *t, const void *out, const void *lse,
+                        const void *dO, int32_t r,
                         double slope, bool softmax, void *dH, void *da1, void *da2, void *dS, void *ws,
                         hipStream_t st)
 {
@@ -518,7 +528,7 @@ hipError_t dispatch_bwd(Shape sh, const fmm_sparse *S_csr, const fmm_sparse *S_c
     if (sh.L == Lv && sh.NV == NVv)                                                              \
         return run_bwd_shape<TH, Acc, Lv, NVv, VW>(                                              \
             S_csr, S_csc, (const TH *)H, (const Acc *)a1, (const Acc *)a2, (const Acc *)s, (const Acc *)t, \
-            (const Acc *)out, (const Acc *)dO, r, (Acc)slope, softmax, (Acc *)dH, (Acc *)da1, (Acc *)da2, \
+            (const Acc *)out, (const Acc *)lse, (const Acc *)dO, r, (Acc)slope, softmax, (Acc *)dH, (Acc *)da1, (Acc *)da2, \
             (Acc *)dS, (char *)ws, st);
     BWD_SHAPES(BWD_CASE)
 #undef BWD_CASE
@@ -543,7 +553,8 @@ fmm_status fmm_gat_backward_workspace(const fmm_sparse *S_csr, const fmm_sparse 
 }
 
 fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *H, const void *a1,
-                            const void *a2, const void *s, const void *t, const void *out, const void *dO, int32_t r,
+                            const void *a2, const void *s, const void *t, const void *out, const void *lse,
+                            const void *dO, int32_t r,
                             int32_t dtype, double negative_slope, int32_t flags, void *dH, void *da1, void *da2,
                             void *dS, void *ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -557,6 +568,7 @@ fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, co
     if (!S_csr->ptr || !S_csc->ptr || (S_csr->nnz > 0 && (!S_csr->idx || !S_csc->idx))) return FMM_ERR_NULL;
     if (!a1 || !a2 || !da1 || !da2) return FMM_ERR_NULL;
     if (n > 0 && (!H || !s || !t || !out || !dO || !dH)) return FMM_ERR_NULL;
+    if (n > 0 && (flags & FMM_GAT_SOFTMAX) && !lse) return FMM_ERR_NULL;
     for (const fmm_sparse *S : {S_csr, S_csc}) {
         if (S->n_chunks < 0 || S->n_splits < 0) return FMM_ERR_DIM;
         if (S->n_chunks > 0 && (!S->chunks || !S->splits || S->long_len < 1)) return FMM_ERR_NULL;
@@ -573,14 +585,14 @@ fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, co
         if (vw == 4 && (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)))
             return FMM_ERR_UNSUPPORTED;
         const Shape sh = bwd_shape(r, vw);
-        e = vw == 4 ? dispatch_bwd<float, float, 4>(sh, S_csr, S_csc, H, a1, a2, s, t, out, dO, r, negative_slope,
+        e = vw == 4 ? dispatch_bwd<float, float, 4>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                     softmax, dH, da1, da2, dS, ws, stream)
-                    : dispatch_bwd<float, float, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, dO, r, negative_slope,
+                    : dispatch_bwd<float, float, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                     softmax, dH, da1, da2, dS, ws, stream);
     } else if (dtype == FMM_BF16) {
         if (r % 8 != 0 || r > 1024) return FMM_ERR_DTYPE;
         if (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)) return FMM_ERR_UNSUPPORTED;
-        e = dispatch_bwd<bf16_t, float, 8>(bwd_shape(r, 8), S_csr, S_csc, H, a1, a2, s, t, out, dO, r,
+        e = dispatch_bwd<bf16_t, float, 8>(bwd_shape(r, 8), S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r,
                                            negative_slope, softmax, dH, da1, da2, dS, ws, stream);
     } else if (dtype == FMM_F64) {
         const int vw = r % 2 == 0 ? 2 : 1;
@@ -588,9 +600,9 @@ fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, co
         if (vw == 2 && (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)))
             return FMM_ERR_UNSUPPORTED;
         const Shape sh = bwd_shape(r, vw);
-        e = vw == 2 ? dispatch_bwd<double, double, 2>(sh, S_csr, S_csc, H, a1, a2, s, t, out, dO, r, negative_slope,
+        e = vw == 2 ? dispatch_bwd<double, double, 2>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                       softmax, dH, da1, da2, dS, ws, stream)
-                    : dispatch_bwd<double, double, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, dO, r, negative_slope,
+                    : dispatch_bwd<double, double, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                       softmax, dH, da1, da2, dS, ws, stream);
     } else {
         return FMM_ERR_DTYPE;

@@ -715,9 +715,10 @@ def gat_scores(H, a1, a2):
     return s, t
 
 
-def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=None):
+def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=None, lse=None):
     """One graph-attention head (Section VI-E): out_i = sum_j w_ij H_j with
-    w = LeakyReLU(S_ij (a1.H_i + a2.H_j)), row-softmaxed when ``softmax``."""
+    w = LeakyReLU(S_ij (a1.H_i + a2.H_j)), row-softmaxed when ``softmax``.  With the
+    softmax, ``lse`` (n values) receives each row's log-sum-exp for the adjoint."""
     if P.m != P.n:
         raise ValueError("graph attention needs a square pattern")
     r = H.shape[1]
@@ -733,21 +734,27 @@ def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=Non
         if ws is None:
             ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
             P._ws_cache[("gat", nb.value)] = ws
+    if lse is not None and (lse.numel() != P.m or lse.dtype != odt or lse.device != P.device):
+        raise ValueError(f"lse must hold {P.m} {odt} values on {P.device}")
     C.call("fmm_gat_forward", ctypes.byref(P.csr), _ptr(s), _ptr(t), _ptr(H), r, dcode, float(negative_slope),
-           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(ws), nb.value, _stream())
+           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(lse), _ptr(ws), nb.value, _stream())
     return out
 
 
-def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=True, want_dS=False):
+def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=True, want_dS=False, lse=None):
     """Adjoint of gat_forward: (dH, da1, da2, dS) for upstream gradient dO, from the
-    forward's output ``out`` (dS, the gradient for S's stored values in CSR order, only
-    with want_dS)."""
+    forward's output ``out`` and, with the softmax, its ``lse`` (recomputed by a forward
+    call when not given).  dS, the gradient for S's stored values in CSR order, only
+    with want_dS."""
     r = H.shape[1]
     _check_dense("H", H, P.n, r, P.device)
     dcode, odt = _common(P, H, None)
     _check_dense("out", out, P.m, r, P.device)
     dO = dO.contiguous()
     _check_dense("dO", dO, P.m, r, P.device)
+    if softmax and lse is None:
+        lse = torch.empty(P.m, dtype=odt, device=P.device)
+        gat_forward(P, H, a1, a2, negative_slope, True, out=torch.empty_like(out), lse=lse)
     s, t = gat_scores(H, a1, a2)
     dH = torch.empty(P.n, r, dtype=odt, device=P.device)
     da1 = torch.empty(r, dtype=odt, device=P.device)
@@ -760,7 +767,8 @@ def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=Tru
         ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
         P._ws_cache[("gat_bwd", nb.value)] = ws
     C.call("fmm_gat_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(H), _ptr(a1.contiguous()),
-           _ptr(a2.contiguous()), _ptr(s), _ptr(t), _ptr(out), _ptr(dO), r, dcode, float(negative_slope),
+           _ptr(a2.contiguous()), _ptr(s), _ptr(t), _ptr(out), _ptr(lse if softmax else None), _ptr(dO), r, dcode,
+           float(negative_slope),
            C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(dH), _ptr(da1), _ptr(da2), _ptr(dS), _ptr(ws), nb.value,
            _stream())
     return dH, da1, da2, (dS[:P.nnz] if want_dS else None)
@@ -770,8 +778,9 @@ class _GAT(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P, H, a1, a2, values, negative_slope, softmax):
         Q = P.with_values(values) if values is not None else P
-        out = gat_forward(Q, H, a1, a2, negative_slope=negative_slope, softmax=softmax)
-        ctx.Q, ctx.slope, ctx.softmax = Q, negative_slope, softmax
+        lse = torch.empty(P.m, dtype=_out_dtype(dtype_code(H)), device=P.device) if softmax else None
+        out = gat_forward(Q, H, a1, a2, negative_slope=negative_slope, softmax=softmax, lse=lse)
+        ctx.Q, ctx.slope, ctx.softmax, ctx.lse = Q, negative_slope, softmax, lse
         ctx.save_for_backward(H, a1, a2, out)
         return out
 
@@ -779,7 +788,8 @@ class _GAT(torch.autograd.Function):
     def backward(ctx, dO):
         H, a1, a2, out = ctx.saved_tensors
         want_dS = ctx.needs_input_grad[4]
-        dH, da1, da2, dS = gat_backward(ctx.Q, H, a1, a2, out, dO, ctx.slope, ctx.softmax, want_dS=want_dS)
+        dH, da1, da2, dS = gat_backward(ctx.Q, H, a1, a2, out, dO, ctx.slope, ctx.softmax, want_dS=want_dS,
+                                        lse=ctx.lse)
         return None, dH, da1, da2, dS, None, None
 
 

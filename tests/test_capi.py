@@ -211,9 +211,9 @@ def test_gat_backward_argument_errors():
     assert lib.fmm_gat_backward_workspace(ctypes.byref(dr), ctypes.byref(dc), 8, 0, ctypes.byref(nb)) == 0
     assert lib.fmm_gat_backward_workspace(ctypes.byref(dr), ctypes.byref(dc), 8, 7, ctypes.byref(nb)) == -3
 
-    def call(S1=dr, S2=dc, r=8, dtype=0, flags=1, ws=FAKE, wsb=None, dH=FAKE, da1=FAKE):
+    def call(S1=dr, S2=dc, r=8, dtype=0, flags=1, ws=FAKE, wsb=None, dH=FAKE, da1=FAKE, lse=FAKE):
         return lib.fmm_gat_backward(ctypes.byref(S1) if S1 is not None else None, ctypes.byref(S2), FAKE, FAKE, FAKE,
-                                    FAKE, FAKE, FAKE, FAKE, r, dtype, 0.2, flags, dH, da1, FAKE, None, ws,
+                                    FAKE, FAKE, FAKE, lse, FAKE, r, dtype, 0.2, flags, dH, da1, FAKE, None, ws,
                                     nb.value if wsb is None else wsb, None)
     assert call(S1=None) == -1
     assert call(S1=_desc(orient=C.FMM_CSC, rows=5, cols=5)) == -4
@@ -224,3 +224,4 @@ def test_gat_backward_argument_errors():
     assert call(wsb=0) == -7
     assert call(ws=FAKE + 16) == -7                              # workspace is 256-byte aligned
     assert call(r=12, dtype=1) == -3                             # bf16 needs r % 8 == 0
+    assert call(lse=None) == -1                                  # the softmax adjoint needs the forward's lse
