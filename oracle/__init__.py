@@ -368,10 +368,10 @@ def gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True, use_val=True):
     x = v * score
     w = gat_edges(S, s, t, slope, softmax, use_val)
     dw = sddmm(S, dO, H, val=None)
+    # np.add.at adds the terms one at a time in stored order (unbuffered), like a loop
     if softmax:
         D = np.zeros(S.m)
-        for p in range(cols.shape[0]):  # row sums in stored order
-            D[rows[p]] += w[p] * dw[p]
+        np.add.at(D, rows, w * dw)
         de = w * (dw - D[rows])
     else:
         de = dw
@@ -379,9 +379,8 @@ def gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True, use_val=True):
     g = dx * v
     ds = np.zeros(n)
     dt = np.zeros(n)
-    for p in range(cols.shape[0]):
-        ds[rows[p]] += g[p]
-        dt[cols[p]] += g[p]
+    np.add.at(ds, rows, g)
+    np.add.at(dt, cols, g)
     dH = spmm_b(S, w, dO) + np.outer(ds, a1) + np.outer(dt, a2)
     da1 = H.T @ ds
     da2 = H.T @ dt

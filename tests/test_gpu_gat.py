@@ -223,3 +223,25 @@ def test_gat_autograd_and_gradcheck(softmax):
             dev(np.asarray(Ss.val, np.float64)).requires_grad_(True))
     assert torch.autograd.gradcheck(lambda h, x, y, v: F.gat(Ps, h, x, y, values=v, softmax=softmax), args,
                                     eps=1e-6, atol=1e-8)
+
+
+@pytest.mark.timeout(600)
+def test_gat_backward_rmat20_r128_full():
+    """The adjoint at the benchmark's size (R-MAT scale 20, 16.1M entries, r = 128, the
+    pattern's default split and line order), every output against the oracle."""
+    w = workload("rmat20_ef16_r64")
+    S = w["S"]
+    r = 128
+    H = dense_normal(S.n, r, 630)
+    a1 = dense_normal(1, r, 631, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 632, sigma=r ** -0.5)[0]
+    dO = dense_normal(S.m, r, 633)
+    log(f"gat backward rmat20 r=128 nnz={S.nnz}")
+    P = F.Pattern.from_csr(S)
+    Hd, a1d, a2d = dev(H), dev(a1), dev(a2)
+    lse = torch.empty(S.m, device="cuda")
+    out = F.gat_forward(P, Hd, a1d, a2d, softmax=True, lse=lse)
+    dH, da1, da2, dS = F.gat_backward(P, Hd, a1d, a2d, out, dev(dO), softmax=True, want_dS=True, lse=lse)
+    ref = oracle.gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True)
+    for name, got, want in zip(("dH", "da1", "da2", "dS"), (dH, da1, da2, dS), ref):
+        _gate_max(f"rmat20 {name}", host(got), want, TOL_F32)
