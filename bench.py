@@ -671,6 +671,15 @@ def main():
     op = 4 if dom == "bwd_col" else 3
     kernel_key = f"line_kernel<{op}, float, float, float, float, {L}, {NV}, {VW}, {U}>"
     traffic = load_traffic(args.workload, kernel_key)
+
+    def pass_key(kind):
+        o = CA.FMM_CSC if kind == "bwd_col" else CA.FMM_CSR
+        Lk, NVk, VWk, Uk = P.launch_shape(o, kind == "bwd_col", r, CA.FMM_F32)
+        return f"line_kernel<{4 if kind == 'bwd_col' else 3}, float, float, float, float, {Lk}, {NVk}, {VWk}, {Uk}>"
+    # counter-measured bytes of the whole step (the three passes' instantiations), when
+    # the committed counter summary covers them
+    pass_traffic = [load_traffic(args.workload, pass_key(k)) for k in kinds]
+    step_traffic = None if any(x is None for x in pass_traffic) else sum(pass_traffic)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
@@ -679,7 +688,10 @@ def main():
                 "kernel_ms": round(kt[dom], 4), "bytes_per_launch": int(dom_bytes),
                 "bytes_model": "gather (each stored entry fetches its dense row(s))",
                 "frac_compulsory_bytes": round(kernel_bytes_min(dom, m, n, nnz, r, e) / (kt[dom] * 1e-3) / 1e9
-                                               / HBM_PEAK_GBS, 4)}
+                                               / HBM_PEAK_GBS, 4),
+                "step_traffic": None if step_traffic is None else int(step_traffic),
+                "step_traffic_frac": None if step_traffic is None else
+                round(step_traffic / (sum(kt.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     variants = {}
     if not args.no_variants:
@@ -749,7 +761,27 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             variants[f"fusedmm_b_fwd_{'fused' if fused else 'unfused'}_ms"] = round(e0.elapsed_time(e1) / vsteps, 4)
-        del Cb, Rb
+        # FusedMMB training step: forward (on the transposed copy), then the adjoint's dB
+        # pass on the transposed copy and its two-row dA pass on the CSR
+        Gb = torch.from_numpy(np.ascontiguousarray(w["B"][:, ::-1])).to(dev)  # an n x r upstream gradient
+        dAb = torch.empty(m, r, dtype=torch.float32, device=dev)
+        dBb = torch.empty(n, r, dtype=torch.float32, device=dev)
+
+        def b_step():
+            F.fusedmm_b_raw(P, A, B, out=Cb)
+            F.fusedmm_b_backward_raw(P, A, B, Gb, dA=dAb, dB=dBb)
+        for _ in range(2):
+            b_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(vsteps):
+            b_step()
+        e1.record()
+        torch.cuda.synchronize()
+        tb = e0.elapsed_time(e1) / vsteps
+        variants["fusedmm_b_step_fused_f32"] = {"ms_per_step": round(tb, 4), "gflops": round(flops / tb / 1e6, 1)}
+        del Cb, Rb, Gb, dAb, dBb
         variants["pattern_prep_s"] = round(prep_s, 3)
         variants["step_bytes_gather_model"] = int(step_bytes)
         variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)
