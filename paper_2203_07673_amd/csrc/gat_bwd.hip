@@ -44,13 +44,41 @@ template <class Acc> __device__ __forceinline__ Acc widen(float x) { return Acc(
 template <class Acc> __device__ __forceinline__ Acc widen(double x) { return Acc(x); }
 template <class Acc> __device__ __forceinline__ Acc widen(bf16_t x) { return Acc(__uint_as_float((uint32_t)x << 16)); }
 
+// The three per-row scalars the column pass gathers for every entry, packed so that one
+// 16-byte (float) or 32-byte (double) load fetches them: s_i, lse_i, D_i.
+template <class Acc> struct RowScalars;
+template <> struct RowScalars<float> {
+    float4 v;
+    __device__ __forceinline__ void load(const void *base, int32_t i) { v = static_cast<const float4 *>(base)[i]; }
+    static __device__ __forceinline__ void store(void *base, int32_t i, float s, float l, float d) {
+        static_cast<float4 *>(base)[i] = make_float4(s, l, d, 0.f);
+    }
+    __device__ __forceinline__ float s() const { return v.x; }
+    __device__ __forceinline__ float lse() const { return v.y; }
+    __device__ __forceinline__ float D() const { return v.z; }
+};
+template <> struct RowScalars<double> {
+    double2 a, b;
+    __device__ __forceinline__ void load(const void *base, int32_t i) {
+        a = static_cast<const double2 *>(base)[2 * i];
+        b = static_cast<const double2 *>(base)[2 * i + 1];
+    }
+    static __device__ __forceinline__ void store(void *base, int32_t i, double s, double l, double d) {
+        static_cast<double2 *>(base)[2 * i] = make_double2(s, l);
+        static_cast<double2 *>(base)[2 * i + 1] = make_double2(d, 0.0);
+    }
+    __device__ __forceinline__ double s() const { return a.x; }
+    __device__ __forceinline__ double lse() const { return a.y; }
+    __device__ __forceinline__ double D() const { return b.x; }
+};
+
 struct GatBwdArgs {
     int32_t nlines, r;
     const int32_t *ptr, *idx;
     const void *val;          // S's values in this orientation (Acc), NULL = 1
     const void *s, *t;        // scores (Acc, per node)
     const void *lse;          // per row log-sum-exp from the forward (softmax; Acc)
-    void *D;                  // per row <dO_i, out_i> (written by the row pass, read by the column pass)
+    void *rs;                 // packed per-row (s_i, lse_i, D_i): written by the row pass, gathered by the column pass
     const void *out;          // forward output (row pass)
     const void *a1, *a2;      // attention vectors (column pass)
     const void *ds;           // ds from the row pass (column pass)
@@ -158,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
     }
     // D_i = <dO_i, out_i> (= sum_j w_ij dw_ij); every chunk of a split row writes the same bits
     const Acc D_i = group_sum<L>(dd);
-    if (lane == 0) static_cast<Acc *>(a.D)[line] = D_i;
+    if (lane == 0) RowScalars<Acc>::store(a.rs, line, si, lse_i, D_i);
     Acc dsum = Acc(0);
     // indices and values of the next batch are loaded while this batch's rows arrive
     int32_t j[U], jn[U];
@@ -225,10 +253,6 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
     const TH *H = static_cast<const TH *>(a.held);
     const Acc *dO = static_cast<const Acc *>(a.gath);
     const Acc *val = static_cast<const Acc *>(a.val);
-    const Acc *s = static_cast<const Acc *>(a.s);
-    const Acc *lse = static_cast<const Acc *>(a.lse);
-    const Acc *D = static_cast<const Acc *>(a.D);
-    const bool softmax_c = a.softmax != 0;
     const Acc tj = static_cast<const Acc *>(a.t)[line];
     const Acc slope = Acc(a.slope);
     const bool softmax = a.softmax != 0;
@@ -254,15 +278,13 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
     if (begin < end) load_entries<Acc, U>(a.idx, val, begin, end, i, v);
     for (int32_t p0 = begin; p0 < end; p0 += U) {
         bool ok[U];
-        Acc si[U], li[U], Di[U];
+        RowScalars<Acc> rsc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) ok[u] = p0 + u < end;
         Raw<Acc, VW> g[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            si[u] = s[i[u]];
-            li[u] = softmax_c ? lse[i[u]] : Acc(0);
-            Di[u] = D[i[u]];
+            rsc[u].load(a.rs, i[u]);
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 if (ok[u] && act[q]) g[u][q].load(dO + (size_t)i[u] * r + off[q]);
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
             Acc w, dx;
-            entry_grad<Acc>(v[u], si[u] + tj, li[u], Di[u], dw[u], slope, softmax, w, dx);
+            entry_grad<Acc>(v[u], rsc[u].s() + tj, rsc[u].lse(), rsc[u].D(), dw[u], slope, softmax, w, dx);
             dtsum += dx * v[u];
 #pragma unroll
             for (int q = 0; q < NV; ++q)
@@ -383,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_reduce_kernel(int32_t nb, int3
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t D, ds, dt, psc_r, pvec_c, psc_c, pblk, total;
+    size_t rs, ds, dt, psc_r, pvec_c, psc_c, pblk, total;
 };
 
 BwdLayout bwd_layout(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, size_t ob)
@@ -394,7 +416,7 @@ BwdLayout bwd_layout(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r
     const int64_t nb = (n + kFinishRows - 1) / kFinishRows;
     BwdLayout l;
     size_t o = 0;
-    l.D = o; o += al256((size_t)n * ob);
+    l.rs = o; o += al256((size_t)n * 4 * ob);
     l.ds = o; o += al256((size_t)n * ob);
     l.dt = o; o += al256((size_t)n * ob);
     l.psc_r = o; o += al256((size_t)ncr * ob);
@@ -418,10 +440,11 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
                          Acc slope, bool softmax, Acc *dH, Acc *da1, Acc *da2, Acc *dS, char *ws, hipStream_t st)
 {
     constexpr int GPB = kBlock / L;
-    constexpr int U = NV == 1 ? 8 : 4;
+    constexpr int UR = NV == 1 ? 8 : 4;  // batch depth of the row pass
+    constexpr int UC = NV == 1 ? 4 : 2;  // and of the column pass (more live registers per entry)
     const int32_t n = S_csr->rows;
     const BwdLayout lay = bwd_layout(S_csr, S_csc, r, sizeof(Acc));
-    Acc *D = reinterpret_cast<Acc *>(ws + lay.D);
+    void *rsb = ws + lay.rs;
     Acc *ds = reinterpret_cast<Acc *>(ws + lay.ds);
     Acc *dt = reinterpret_cast<Acc *>(ws + lay.dt);
     hipError_t e;
@@ -438,7 +461,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.s = s;
     a.t = t;
     a.lse = lse;
-    a.D = D;
+    a.rs = rsb;
     a.slope = (double)slope;
     a.softmax = softmax ? 1 : 0;
     // (1) row pass: D, ds, dS
@@ -457,7 +480,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.part_sc = ws + lay.psc_r;
     a.dS = dS;
     int64_t nbc = a.n_chunks > 0 ? ((int64_t)a.n_chunks + GPB - 1) / GPB : 0;
-    hipLaunchKernelGGL((gat_bwd_rows_kernel<TH, Acc, L, NV, VW, U>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
+    hipLaunchKernelGGL((gat_bwd_rows_kernel<TH, Acc, L, NV, VW, UR>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
                        0, st, a, (int32_t)nbc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (S_csr->n_chunks > 0 && S_csr->n_splits > 0) {
@@ -487,7 +510,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.part_sc = ws + lay.psc_c;
     a.dS = nullptr;
     nbc = a.n_chunks > 0 ? ((int64_t)a.n_chunks + GPB - 1) / GPB : 0;
-    hipLaunchKernelGGL((gat_bwd_cols_kernel<TH, Acc, L, NV, VW, U>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
+    hipLaunchKernelGGL((gat_bwd_cols_kernel<TH, Acc, L, NV, VW, UC>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
                        0, st, a, (int32_t)nbc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // (3) split columns: merge their chunks, then add their rank-one terms
