@@ -204,6 +204,7 @@ class Pattern:
         if s.dtype != self.val_dtype or s.device != self.device:
             raise TypeError(f"values must be {self.val_dtype} on {self.device}")
         Q = copy.copy(self)
+        Q._orders = dict(self._orders)  # Q's own tuning changes must not swap tensors under self's descriptors
         Q.val = s.detach().contiguous()
         Q.valT = torch.empty(max(1, self.nnz), dtype=self.val_dtype, device=self.device)
         vcode = C.FMM_F64 if self.val_dtype == torch.float64 else C.FMM_F32

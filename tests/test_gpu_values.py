@@ -131,3 +131,22 @@ def test_learned_values_gradcheck_fp64():
                                         eps=1e-6, atol=1e-8)
         assert torch.autograd.gradcheck(lambda a, b, v: F.fusedmm_b(P, a, b, fused=fused, values=v), (At, Bt, st),
                                         eps=1e-6, atol=1e-8)
+
+
+def test_with_values_keeps_the_original_pattern_intact():
+    """Tuning a values view must not touch the pattern it came from (their descriptors
+    point at their own schedule and order tensors)."""
+    S = rmat(10, 8, seed=550)
+    P = F.Pattern.from_csr(S, long_len=64, chunk=32, line_order=True)
+    A, B = dev(dense_normal(S.m, 16, 551)), dev(dense_normal(S.n, 16, 552))
+    log("with_values independence")
+    before = F.fusedmm_a_raw(P, A, B)[0].clone()
+    Q = P.with_values(P.val.clone())
+    Q.set_line_order(0, False)
+    Q.set_line_order(1, False)
+    Q.set_split(1, 16)
+    torch.cuda.synchronize()
+    assert P.orders["csr"] is not None and P.orders["csc"] is not None and P.splits["csc"] == 64
+    assert torch.equal(F.fusedmm_a_raw(P, A, B)[0], before)
+    # same values and CSR schedule, order off: the order never changes a line's arithmetic
+    assert torch.equal(F.fusedmm_a_raw(Q, A, B)[0], before)
