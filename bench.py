@@ -384,6 +384,9 @@ def run_gat(args):
     a = [(torch.from_numpy(dense_normal(1, r, 600 + h, sigma=r ** -0.5)[0]).to(dev),
           torch.from_numpy(dense_normal(1, r, 700 + h, sigma=r ** -0.5)[0]).to(dev)) for h in range(heads)]
     outs = [torch.empty(S.m, r, device=dev) for _ in range(heads)]
+    dOs = [torch.from_numpy(dense_normal(S.m, r, 800 + h)).to(dev) for h in range(heads)]
+    tuning = F.gat_autotune(P, Hs[0], a[0][0], a[0][1], dO=dOs[0], softmax=True)
+    log(f"attention autotuned: {tuning}")
 
     def step(Hl):
         for h in range(heads):
@@ -410,7 +413,6 @@ def run_gat(args):
     tu = timeit(lambda: step_unfused(Hs), args.steps, args.warmup)
 
     # adjoint of every head (dH, da1, da2) from the forward outputs and an upstream gradient
-    dOs = [torch.from_numpy(dense_normal(S.m, r, 800 + h)).to(dev) for h in range(heads)]
 
     lses = [torch.empty(S.m, device=dev) for _ in range(heads)]
 
@@ -435,7 +437,7 @@ def run_gat(args):
            "unfused_f32_ms": round(tu * 1e3, 4), "speedup_fused_f32_vs_unfused_f32": round(tu / t32, 3),
            "backward_f32_ms": round(tb32 * 1e3, 4), "backward_bf16_ms": round(tb16 * 1e3, 4),
            "train_step_f32_ms": round((t32 + tb32) * 1e3, 4),
-           "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3)}
+           "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3), "tuning": tuning}
     print(json.dumps(out), flush=True)
 
 

@@ -21,6 +21,7 @@ from .fusedmm import (  # noqa: F401
     fusedmm_b_backward_values_raw,
     fusedmm_b_raw,
     gat,
+    gat_autotune,
     gat_backward,
     gat_edge_values,
     gat_forward,

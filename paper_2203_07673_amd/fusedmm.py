@@ -25,7 +25,8 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "gat_backward", "gat", "cg_lines", "als_residual",
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "gat_backward", "gat",
+           "gat_autotune", "cg_lines", "als_residual",
            "als_sweep"]
 
 DEFAULT_LONG_LEN = 128
@@ -773,6 +774,51 @@ def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=Tru
            C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(dH), _ptr(da1), _ptr(da2), _ptr(dS), _ptr(ws), nb.value,
            _stream())
     return dH, da1, da2, (dS[:P.nnz] if want_dS else None)
+
+
+def gat_autotune(P: Pattern, H, a1, a2, dO=None, negative_slope=0.2, softmax=True,
+                 split_candidates=SPLIT_CANDIDATES, orders=(False, True), variants=(1, 2)):
+    """Time the attention head (forward, plus the adjoint when dO is given) over split
+    threshold x line order x batch depth, applied to both orientations, and keep the
+    fastest on P.  Returns P.tuning."""
+    r = H.shape[1]
+    odt = _out_dtype(dtype_code(H))
+    out = torch.empty(P.m, r, dtype=odt, device=P.device)
+    lse = torch.empty(P.m, dtype=odt, device=P.device) if softmax else None
+
+    def run():
+        gat_forward(P, H, a1, a2, negative_slope, softmax, out=out, lse=lse)
+        if dO is not None:
+            gat_backward(P, H, a1, a2, out, dO, negative_slope, softmax, lse=lse)
+
+    longest = max(P.max_line(C.FMM_CSR), P.max_line(C.FMM_CSC))
+    cands = [ll for ll in split_candidates if ll < longest] if P._split else []
+    best = None
+    for ll in (cands or [None]):
+        for lo in orders:
+            for o in (C.FMM_CSR, C.FMM_CSC):
+                if ll is not None:
+                    P.set_split(o, ll)
+                P.set_line_order(o, lo)
+            for v in variants:
+                P.set_variant(v, v)
+                run()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    run()
+                e1.record()
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / 3
+                if best is None or ms < best[0]:
+                    best = (ms, ll, lo, v)
+    _, ll, lo, v = best
+    for o in (C.FMM_CSR, C.FMM_CSC):
+        if ll is not None:
+            P.set_split(o, ll)
+        P.set_line_order(o, lo)
+    P.set_variant(v, v)
+    return P.tuning
 
 
 class _GAT(torch.autograd.Function):

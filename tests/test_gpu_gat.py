@@ -245,3 +245,23 @@ def test_gat_backward_rmat20_r128_full():
     ref = oracle.gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True)
     for name, got, want in zip(("dH", "da1", "da2", "dS"), (dH, da1, da2, dS), ref):
         _gate_max(f"rmat20 {name}", host(got), want, TOL_F32)
+
+
+def test_gat_autotune_keeps_results():
+    S = rmat(11, 8, seed=640)
+    r = 32
+    H = dense_normal(S.n, r, 641)
+    a1 = dense_normal(1, r, 642, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 643, sigma=r ** -0.5)[0]
+    dO = dense_normal(S.m, r, 644)
+    log("gat autotune")
+    P = F.Pattern.from_csr(S)
+    tuning = F.gat_autotune(P, dev(H), dev(a1), dev(a2), dO=dev(dO))
+    assert set(tuning) == {"csr", "csc"}
+    lse = torch.empty(S.m, device="cuda")
+    out = F.gat_forward(P, dev(H), dev(a1), dev(a2), lse=lse)
+    ref, mag = _ref(S, H, a1, a2, 0.2, True)
+    gate("tuned forward", host(out), ref, mag, TOL_F32)
+    got = F.gat_backward(P, dev(H), dev(a1), dev(a2), out, dev(dO), want_dS=True, lse=lse)
+    for name, g, want in zip(("dH", "da1", "da2", "dS"), got, oracle.gat_backward(S, H, a1, a2, dO)):
+        _gate_max(f"tuned {name}", host(g), want, TOL_F32)
