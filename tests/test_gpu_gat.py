@@ -265,3 +265,31 @@ def test_gat_autotune_keeps_results():
     got = F.gat_backward(P, dev(H), dev(a1), dev(a2), out, dev(dO), want_dS=True, lse=lse)
     for name, g, want in zip(("dH", "da1", "da2", "dS"), got, oracle.gat_backward(S, H, a1, a2, dO)):
         _gate_max(f"tuned {name}", host(g), want, TOL_F32)
+
+
+def test_gat_backward_edge_cases():
+    """No stored entries (every weight absent: dH = 0 and da = 0), a row without entries
+    among others, and a wide head (r = 512, the L = 64 x NV = 2 shape)."""
+    log("gat backward edge cases")
+    S0 = CsrPattern(5, 5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    P0 = F.Pattern.from_csr(S0)
+    H0 = dev(dense_normal(5, 8, 650))
+    a = dev(dense_normal(1, 8, 651)[0])
+    lse = torch.empty(5, device="cuda")
+    out = F.gat_forward(P0, H0, a, a, lse=lse)
+    dH, da1, da2, dS = F.gat_backward(P0, H0, a, a, out, dev(dense_normal(5, 8, 652)), want_dS=True, lse=lse)
+    assert not host(dH).any() and not host(da1).any() and not host(da2).any() and dS.numel() == 0
+    rp = np.array([0, 2, 2, 5, 6], np.int32)
+    ci = np.array([1, 3, 0, 2, 3, 1], np.int32)
+    S1 = CsrPattern(4, 4, rp, ci, np.linspace(0.5, 1.5, 6).astype(np.float32))
+    for r in (8, 512):
+        H = dense_normal(S1.n, r, 653)
+        a1 = dense_normal(1, r, 654, sigma=r ** -0.5)[0]
+        a2 = dense_normal(1, r, 655, sigma=r ** -0.5)[0]
+        dO = dense_normal(S1.m, r, 656)
+        P1 = F.Pattern.from_csr(S1)
+        lse = torch.empty(4, device="cuda")
+        out = F.gat_forward(P1, dev(H), dev(a1), dev(a2), lse=lse)
+        got = F.gat_backward(P1, dev(H), dev(a1), dev(a2), out, dev(dO), want_dS=True, lse=lse)
+        for name, g, want in zip(("dH", "da1", "da2", "dS"), got, oracle.gat_backward(S1, H, a1, a2, dO)):
+            _gate_max(f"edge r={r} {name}", host(g), want, TOL_F32)

@@ -150,3 +150,24 @@ def test_with_values_keeps_the_original_pattern_intact():
     assert torch.equal(F.fusedmm_a_raw(P, A, B)[0], before)
     # same values and CSR schedule, order off: the order never changes a line's arithmetic
     assert torch.equal(F.fusedmm_a_raw(Q, A, B)[0], before)
+
+
+@pytest.mark.parametrize("r,dtype", [(1024, torch.float32), (512, torch.float64), (1024, torch.bfloat16)])
+def test_value_gradient_widest_rows(r, dtype):
+    S32 = er_exact_degree(96, 80, 7, seed=560)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    S = S32 if dtype != torch.float64 else CsrPattern(S32.m, S32.n, S32.rowptr, S32.colidx, S32.val.astype(np.float64))
+    A, B, G = dense_normal(S.m, r, 561, dtype=npdt), dense_normal(S.n, r, 562, dtype=npdt), dense_normal(S.m, r, 563,
+                                                                                                          dtype=npdt)
+    log(f"values widest r={r} {dtype}")
+    P = F.Pattern.from_csr(S)
+    odt = torch.float64 if dtype == torch.float64 else torch.float32
+    Ad = F.to_bf16(dev(A)) if dtype == torch.bfloat16 else dev(A, dtype)
+    Bd = F.to_bf16(dev(B)) if dtype == torch.bfloat16 else dev(B, dtype)
+    dS, dA = F.fusedmm_a_backward_values_raw(P, Ad, Bd, dev(G, odt), want_dA=True)
+    Aq = oracle.bf16_round(A) if dtype == torch.bfloat16 else A
+    Bq = oracle.bf16_round(B) if dtype == torch.bfloat16 else B
+    ref, mag = _refs(S, Aq, Bq, G, "a")
+    gate(f"widest dS r={r}", host(dS), ref, mag, TOL_F64 if dtype == torch.float64 else TOL_F32)
+    eA, _, mA, _ = ref_fusedmm_a_backward(S, Aq, Bq, G)
+    gate(f"widest dA r={r}", host(dA), eA, mA, TOL_F64 if dtype == torch.float64 else TOL_F32)
