@@ -244,6 +244,11 @@ fmm_status fmm_cg_lines(const fmm_sparse *S, const void *F, int32_t r, int32_t d
                            : dispatch_cg<1>(sh, true, n, r, rhs, Q, X, lambda, R, P, rr, stream);
     if (e != hipSuccess) return hipfail(e);
     for (int32_t it = 0; it < iters; ++it) {
+        if (S->n_chunks == 0) {  // the step fused into the Gram pass: q never reaches memory
+            s = gram_cg_step(S, P, F, r, dtype, lambda, X, R, rr, stream);
+            if (s != FMM_OK) return s;
+            continue;
+        }
         s = gram_apply(S, P, F, r, dtype, Q, ws, ws_bytes, stream);
         if (s != FMM_OK) return s;
         e = vw == 4 ? dispatch_cg<4>(sh, false, n, r, rhs, Q, X, lambda, R, P, rr, stream)

@@ -272,6 +272,32 @@ fmm_status gram_apply(const fmm_sparse *S, const float *H, const void *G, int32_
     FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S, st));
     return FMM_OK;
 }
+// One batched CG step for every line of S fused with the Gram pass (OP_CG): the line's
+// q = sum_j <P_line, G_j> G_j stays in registers and updates X, R, P and rr in place.
+// S must carry no split schedule (a split line's q is only complete after its merge).
+fmm_status gram_cg_step(const fmm_sparse *S, float *P, const void *G, int32_t r, int32_t dtype, float lambda,
+                        float *X, float *R, float *rr, hipStream_t st)
+{
+    Kinds k;
+    FMM_TRY(kinds_for(dtype, r, &k));
+    if (S->n_chunks > 0) return FMM_ERR_UNSUPPORTED;
+    LineArgs a = base_args(S, r, nullptr);
+    a.val = nullptr;
+    a.H = P;
+    a.G1 = G;
+    a.out = nullptr;
+    a.cg_X = X;
+    a.cg_R = R;
+    a.cg_P = P;
+    a.cg_rr = rr;
+    a.cg_lambda = lambda;
+    hipError_t e;
+    if (dtype == FMM_F32) e = launch_lines<OP_CG, float, float, float, float>(a, 0, nullptr, hint(), st);
+    else if (dtype == FMM_BF16) e = launch_lines<OP_CG, float, bf16_t, bf16_t, float>(a, 0, nullptr, hint(), st);
+    else return FMM_ERR_DTYPE;
+    FMM_HIP(e);
+    return FMM_OK;
+}
 }  // namespace fmm
 
 extern "C" {

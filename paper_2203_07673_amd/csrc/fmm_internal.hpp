@@ -44,6 +44,8 @@ hipError_t launch_lines(const LineArgs &a, int32_t n_splits, const int32_t *spli
 // out_line = sum_j <H_line, G_j> G_j.
 fmm_status gram_apply(const fmm_sparse *S, const float *H, const void *G, int32_t r, int32_t dtype, float *out,
                       void *ws, size_t ws_bytes, hipStream_t st);
+fmm_status gram_cg_step(const fmm_sparse *S, float *P, const void *G, int32_t r, int32_t dtype, float lambda,
+                        float *X, float *R, float *rr, hipStream_t st);
 
 // Pattern preparation kernels (pattern.hip).
 size_t scan_workspace_bytes(int64_t n);

@@ -17,6 +17,10 @@
 //   OP_FUSED1S: OP_FUSED1 plus, per entry, V[p] = <H_line, G1_j> <H2_line, G1_j> with a
 //               second held row H2 (the gradient with respect to S's values, written with
 //               the adjoint row pass; out may be NULL)
+//   OP_CG     : OP_FUSED1 on the pattern alone, where the line's sum q = M p is consumed in
+//               registers by one conjugate-gradient step of that line (batched CG of the
+//               ALS application): X, R, P (= H, updated in place) and rr; nothing else
+//               is written
 //
 // Work decomposition.  A group of L lanes (L | 64) owns one line; lane l holds
 // elements k = (v*L + l)*VW + e (v < NV, e < VW) of each r-vector, so one vector
@@ -50,7 +54,7 @@ template <> __device__ __forceinline__ const float *unit_value<float>() { return
 template <> __device__ __forceinline__ const double *unit_value<double>() { return kUnitD; }
 __device__ __forceinline__ const int32_t *zero_index() { return kZeroIdx; }
 
-enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4, OP_FUSED1S = 5 };
+enum { OP_SDDMM = 0, OP_SPMM1 = 1, OP_SPMM2 = 2, OP_FUSED1 = 3, OP_FUSED2 = 4, OP_FUSED1S = 5, OP_CG = 6 };
 
 constexpr int kBlock = 256;
 
@@ -70,6 +74,8 @@ struct LineArgs {
     const void *H2;       // second held matrix (TG2 elements), OP_FUSED1S
     void *out;            // lines x r (Acc), or nnz (Acc) for OP_SDDMM; may be NULL for OP_FUSED1S
     void *values;         // nnz per-entry output (Acc) of OP_FUSED1S, through operm when non-NULL
+    float *cg_X, *cg_R, *cg_P, *cg_rr;  // OP_CG: iterate, residual, direction (the held rows), <R, R>
+    float cg_lambda;                    // OP_CG: ridge term of the line operator
     double beta;
     int32_t long_len;
     int32_t n_chunks;
@@ -322,9 +328,66 @@ struct LineOperands {
     const void *G2;
     const void *H2;  // OP_FUSED1S second held matrix
     void *R;         // per-entry output (nnz): OP_SDDMM, OP_FUSED1S
+    float *cg_X, *cg_R, *cg_P, *cg_rr;  // OP_CG
+    float cg_lambda;
     int32_t r;
     double beta;
 };
+
+// One conjugate-gradient step of one line, with q = M p (the line's sum, in registers)
+// and p (the held row):  alpha = rr / <p, q + lambda p>;  x += alpha p;
+// r -= alpha (q + lambda p);  beta = <r, r>_new / rr;  p = r + beta p;  rr = <r, r>_new.
+// A line with zero residual or curvature keeps its iterate (alpha = beta = 0).
+template <int L, int NV, int VW, class Acc>
+__device__ __forceinline__ void cg_line_step(const LineOperands &o, int32_t line, int lane, const bool *act,
+                                             const int *off, const Acc *h, const Acc *acc)
+{
+    constexpr int E = NV * VW;
+    const size_t base = (size_t)line * o.r;
+    const float lam = o.cg_lambda;
+    float mq[E];
+    float pq = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        mq[e] = float(acc[e]) + lam * float(h[e]);  // inactive lanes hold zeros
+        pq += float(h[e]) * mq[e];
+    }
+    pq = group_sum<L>(pq);
+    const float rr_old = o.cg_rr[line];
+    const float alpha = (rr_old > 0.f && pq > 0.f) ? rr_old / pq : 0.f;
+    float res[E];
+    float rrn = 0.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (!act[v]) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) res[v * VW + e] = 0.f;
+            continue;
+        }
+        float x[VW], rv[VW];
+        Ld<float, VW, float>::run(o.cg_X + base + off[v], x);
+        Ld<float, VW, float>::run(o.cg_R + base + off[v], rv);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            x[e] += alpha * float(h[v * VW + e]);
+            res[v * VW + e] = rv[e] - alpha * mq[v * VW + e];
+            rrn += res[v * VW + e] * res[v * VW + e];
+        }
+        St<float, VW>::run(o.cg_X + base + off[v], x);
+        St<float, VW>::run(o.cg_R + base + off[v], res + v * VW);
+    }
+    rrn = group_sum<L>(rrn);
+    const float beta = rr_old > 0.f ? rrn / rr_old : 0.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (!act[v]) continue;
+        float np[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) np[e] = res[v * VW + e] + beta * float(h[v * VW + e]);
+        St<float, VW>::run(o.cg_P + base + off[v], np);
+    }
+    if (lane == 0) o.cg_rr[line] = rrn;
+}
 
 // Process entries [begin, end) of one major line.  GPL groups of L lanes may share the
 // line (GPL > 1: wavefront-per-line; group gidx takes every GPL-th batch of U entries
@@ -356,7 +419,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     const TG1 *__restrict__ G1 = static_cast<const TG1 *>(o.G1);
     const TG2 *__restrict__ G2 = static_cast<const TG2 *>(o.G2);
 
-    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2 || OP == OP_FUSED1S);
+    constexpr bool kHeld = (OP == OP_SDDMM || OP == OP_FUSED1 || OP == OP_FUSED2 || OP == OP_FUSED1S || OP == OP_CG);
     constexpr bool kHeld2 = (OP == OP_FUSED1S);
     constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
 
@@ -600,6 +663,11 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         }
     }
 
+    if constexpr (OP == OP_CG) {
+        static_assert(GPL == 1, "a CG step needs the whole line in one group");
+        cg_line_step<L, NV, VW>(o, line, lane, act, off, h, acc);
+        return;
+    }
     if constexpr (OP != OP_SDDMM) {
         if (dst == nullptr) return;  // OP_FUSED1S without the row output
         if constexpr (GPL > 1) {
@@ -668,6 +736,11 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
     o.G2 = a.G2;
     o.H2 = a.H2;
     o.R = OP == OP_FUSED1S ? a.values : a.out;
+    o.cg_X = a.cg_X;
+    o.cg_R = a.cg_R;
+    o.cg_P = a.cg_P;
+    o.cg_rr = a.cg_rr;
+    o.cg_lambda = a.cg_lambda;
     o.r = r;
     o.beta = a.beta;
     process_line<OP, TH, TG1, TG2, Acc, L, NV, VW, U, 1>(o, lane, 0, line, begin, end, dst,

@@ -371,7 +371,22 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_da_kernel(int32_t n, int32_t r
     const int64_t r1 = r0 + kFinishRows < n ? r0 + kFinishRows : n;
     for (int k = threadIdx.x; k < r; k += kBlock) {
         Acc p1 = Acc(0), p2 = Acc(0);
-        for (int64_t j = r0; j < r1; ++j) {
+        int64_t j = r0;
+        for (; j + 8 <= r1; j += 8) {  // eight rows' loads in flight, added in row order
+            Acc h[8], a[8], b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                h[u] = widen<Acc>(H[(j + u) * r + k]);
+                a[u] = ds[j + u];
+                b[u] = dt[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                p1 += a[u] * h[u];
+                p2 += b[u] * h[u];
+            }
+        }
+        for (; j < r1; ++j) {
             const Acc h = widen<Acc>(H[j * r + k]);
             p1 += ds[j] * h;
             p2 += dt[j] * h;

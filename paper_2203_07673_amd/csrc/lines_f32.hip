@@ -8,4 +8,5 @@ FMM_INSTANTIATE(OP_SPMM2, float, float, float, float)
 FMM_INSTANTIATE(OP_FUSED1, float, float, float, float)
 FMM_INSTANTIATE(OP_FUSED2, float, float, float, float)
 FMM_INSTANTIATE(OP_FUSED1S, float, float, float, float)
+FMM_INSTANTIATE(OP_CG, float, float, float, float)
 }  // namespace fmm

@@ -24,9 +24,12 @@ def _rowrel(got, ref):
     return float(np.max(np.abs(got - ref).max(axis=1) / np.maximum(den, 1e-3 * np.abs(ref).max())))
 
 
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("iters", [1, 5, 10])
-def test_cg_lines_parity(dtype, iters):
+def test_cg_lines_parity(dtype, iters, split):
+    """split: CG steps as a Gram pass plus a step kernel (a split schedule needs its merge);
+    without one, each step is fused into the Gram pass."""
     S = rmat(11, 8, seed=520)
     r, lam = 32, 1.0
     Fa = dense_normal(S.n, r, 521, sigma=r ** -0.5)
@@ -35,8 +38,9 @@ def test_cg_lines_parity(dtype, iters):
     rhs_b = dense_normal(S.n, r, 524)
     X0a = dense_normal(S.m, r, 525)
     X0b = dense_normal(S.n, r, 526)
-    log(f"cg dtype={dtype} iters={iters}")
-    P = F.Pattern.from_csr(S, long_len=64, chunk=32)
+    log(f"cg dtype={dtype} iters={iters} split={split}")
+    P = F.Pattern.from_csr(S, long_len=64, chunk=32, split=split)
+    assert (P.schedules["csr"] is not None) == split
     ST = oracle.transpose(S)
     for orient, Fm, rhs, X0, pat in ((C.FMM_CSR, Fa, rhs_a, X0a, S), (C.FMM_CSC, Fb, rhs_b, X0b, ST)):
         Fd = F.to_bf16(dev(Fm)) if dtype == torch.bfloat16 else dev(Fm)
