@@ -282,8 +282,10 @@ fmm_status fmm_fusedmm_a(const fmm_sparse *S_csr, const void *A, const void *B, 
 /*
  * FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A) (Section II):
  * C'_j: = sum_i S_ij <A_i:, B_j:> A_i:, C': cols x r, computed on the CSC descriptor
- * as FusedMMA(S^T, B, A) (Section IV-B's transposed copy).  UNFUSED: R_ws receives
- * R in CSC order.
+ * as FusedMMA(S^T, B, A) (Section IV-B's transposed copy).  UNFUSED: the SDDMM on the
+ * transposed copy writes R into R_ws in S's own (CSR) order through S_csc->perm (the
+ * layout of the paper's unfused sequence), and the SpMMB reads it back through perm;
+ * S_csc->perm is required.
  */
 fmm_status fmm_fusedmm_b(const fmm_sparse *S_csc, const void *A, const void *B, int32_t r,
                          int32_t dtype, void *C, int32_t flags, void *R_ws, void *ws,
@@ -323,8 +325,8 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
  *   dP = S * (A dC^T)
  *   dA = dP B + R dC           (row pass on S_csr)
  *   dB = dP^T A                = FusedMMB(S, A, dC)            (column pass on S_csc)
- * Same flag and workspace rules as fmm_fusedmm_a_backward (R_ws from the unfused
- * FusedMMB forward is in CSC order; dP_ws is written in CSR order).
+ * Same flag and workspace rules as fmm_fusedmm_a_backward (R_ws, from the unfused
+ * FusedMMB forward, and dP_ws are both in CSR order).
  */
 fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
                                   const void *B, const void *dC, int32_t r, int32_t dtype,
