@@ -123,11 +123,24 @@ def _short_kernel(name):
     return name[:120]
 
 
+def calibration_dispatches(per):
+    """Dispatch ids of the plain copies --calibrate-copy ran: the copy-kernel dispatches
+    whose counter reads within 1% of the largest copy reading of the run (the
+    calibration copy of COPY_BYTES is larger than any copy the workload makes)."""
+    copies = {i: v for i, (k, v) in per.items() if "copy" in k.lower()}
+    if not copies:
+        return []
+    top = max(copies.values())
+    return sorted(i for i, v in copies.items() if top > 0 and abs(v - top) < 0.01 * top)
+
+
 def pmc_summary(fetch_dir, write_dir, out_json, command=""):
     """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from two counter runs of the
     same command, with scale factors from the plain device copy of COPY_BYTES bytes that
-    --calibrate-copy ran (found as the copy dispatches writing COPY_BYTES; the two runs
-    number their dispatches identically)."""
+    --calibrate-copy ran.  The copies are found in each run on its own, as its largest
+    copy dispatches (those of the write run must each write COPY_BYTES): the autotuner
+    may make a different number of launches in the two runs, so their dispatch numbers
+    need not line up."""
     runs = {}
     for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         runs[counter] = {}
@@ -135,17 +148,21 @@ def pmc_summary(fetch_dir, write_dir, out_json, command=""):
             if row.get("Counter_Name") == counter:
                 runs[counter][int(row["Dispatch_Id"])] = (row["Kernel_Name"], float(row["Counter_Value"]))
     want_kib = COPY_BYTES / 1024.0
-    calib = [i for i, (k, v) in runs["WRITE_SIZE"].items()
-             if "copy" in k.lower() and abs(v - want_kib) < 0.01 * want_kib and i in runs["FETCH_SIZE"]]
+    calib = {c: calibration_dispatches(per) for c, per in runs.items()}
     scale = {"FETCH_SIZE": None, "WRITE_SIZE": None}
-    if calib:
+    w = calib["WRITE_SIZE"]
+    # the write run names the copies (each writes COPY_BYTES); the fetch run must hold as many
+    if w and all(abs(runs["WRITE_SIZE"][i][1] - want_kib) < 0.01 * want_kib for i in w) \
+            and len(calib["FETCH_SIZE"]) == len(w):
         for c in scale:
-            mean = sum(runs[c][i][1] for i in calib) / len(calib)
+            mean = sum(runs[c][i][1] for i in calib[c]) / len(calib[c])
             scale[c] = want_kib / mean if mean > 0 else None
+    else:
+        calib = {c: [] for c in runs}
     kernels = {}
     for c, per in runs.items():
         for i, (k, v) in per.items():
-            if i in calib:
+            if i in calib[c]:
                 continue
             kernels.setdefault(_short_kernel(k), {}).setdefault(c, []).append(v)
     summary = {}
@@ -153,7 +170,7 @@ def pmc_summary(fetch_dir, write_dir, out_json, command=""):
         summary[k] = {c: sum(x) / len(x) for c, x in v.items()}
         summary[k]["dispatches"] = max(len(x) for x in v.values())
     out = {"command": command, "source_hash": source_hash(), "copy_bytes": COPY_BYTES,
-           "copy_dispatches": sorted(calib), "scale": scale,
+           "copy_dispatches": {c: sorted(v) for c, v in calib.items()}, "scale": scale,
            "note": "KiB per dispatch as the counters read them; bytes = (FETCH*scale_f + WRITE*scale_w)*1024",
            "kernels": summary}
     with open(out_json, "w") as fh:

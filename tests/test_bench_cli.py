@@ -35,3 +35,35 @@ def test_committed_counter_summaries_parse():
             assert t["scale"]["FETCH_SIZE"] and t["scale"]["WRITE_SIZE"]
             assert t["command"].startswith("rocprofv3")
             assert any(k.startswith("line_kernel<") for k in t["kernels"])
+
+
+def _write_pmc(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "pmc_counter_collection.csv"), "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, k, v in rows:
+            fh.write(f'{i},"{k}",{counter},{v}\n')
+
+
+def test_counter_calibration_when_the_runs_number_dispatches_differently(tmp_path):
+    """The two counter runs may differ in launch count (the autotuner's choices): the
+    calibration copies are found in each run by themselves and scale each counter."""
+    kib = bench.COPY_BYTES / 1024.0
+    lk = "void fmm::line_kernel<3, float, float, float, float, 32, 1, 4, 2>(fmm::LineArgs)"
+    fetch = [(1, "__amd_rocclr_copyBuffer", 2.0), (2, lk, 100.0), (3, lk, 100.0)] + \
+        [(10 + i, "__amd_rocclr_copyBuffer", kib / 2) for i in range(3)]
+    write = [(1, "__amd_rocclr_copyBuffer", 4.0), (2, lk, 30.0), (3, lk, 30.0), (4, lk, 30.0), (5, lk, 30.0)] + \
+        [(20 + i, "__amd_rocclr_copyBuffer", kib) for i in range(3)]
+    _write_pmc(str(tmp_path / "f"), "FETCH_SIZE", fetch)
+    _write_pmc(str(tmp_path / "w"), "WRITE_SIZE", write)
+    out = str(tmp_path / "t.json")
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), out, command="rocprofv3 test")
+    t = json.load(open(out))
+    assert t["scale"] == {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+    assert t["copy_dispatches"] == {"FETCH_SIZE": [10, 11, 12], "WRITE_SIZE": [20, 21, 22]}
+    k = t["kernels"]["line_kernel<3, float, float, float, float, 32, 1, 4, 2>"]
+    assert k["FETCH_SIZE"] == 100.0 and k["WRITE_SIZE"] == 30.0 and k["dispatches"] == 4
+    # a write run whose largest copy is not the calibration size gives no scale at all
+    _write_pmc(str(tmp_path / "w2"), "WRITE_SIZE", write[:5])
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w2"), out)
+    assert json.load(open(out))["scale"] == {"FETCH_SIZE": None, "WRITE_SIZE": None}
