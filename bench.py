@@ -216,15 +216,16 @@ def counter_table(out_md, runs, command=""):
         name, dirs = spec.split("=", 1)
         trace_dir, fetch_dir, write_dir = dirs.split(":")
         fetch, write = _pmc_per_key(fetch_dir, "FETCH_SIZE"), _pmc_per_key(write_dir, "WRITE_SIZE")
-        calib = [i for i, (k, v) in write.items() if "copy" in k.lower() and abs(v - want_kib) < 0.01 * want_kib
-                 and i in fetch]
-        if not calib:
+        cf, cw = calibration_dispatches(fetch), calibration_dispatches(write)
+        if not cw or len(cf) != len(cw) or any(abs(write[i][1] - want_kib) >= 0.01 * want_kib for i in cw):
             raise SystemExit(f"{name}: no calibration copy found")
-        sf = want_kib / (sum(fetch[i][1] for i in calib) / len(calib))
-        sw = want_kib / (sum(write[i][1] for i in calib) / len(calib))
+        sf = want_kib / (sum(fetch[i][1] for i in cf) / len(cf))
+        sw = want_kib / (sum(write[i][1] for i in cw) / len(cw))
         byk = {}
+        # a --profile-step command makes the same launches in its three runs, so its
+        # dispatches pair up by number
         for i, (k, v) in fetch.items():
-            if i in calib or i not in write:
+            if i in cf or i in cw or i not in write:
                 continue
             b = (v * sf + write[i][1] * sw) * 1024.0
             byk.setdefault(k, []).append(b)
@@ -529,6 +530,59 @@ def calibrate_copy(dev):
     torch.cuda.synchronize()
 
 
+def copy_ceiling(dev, reps=10):
+    """Measured HBM ceilings on contiguous traffic of COPY_BYTES: the library's plain
+    copy kernel (read + write, 2 x COPY_BYTES moved) and its read-only pass (COPY_BYTES
+    moved), both on the current stream; torch's device-to-device copy for comparison."""
+    import torch
+
+    import paper_2203_07673_amd as F
+
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def median_ms(fn):
+        for _ in range(2):
+            fn()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    t_copy = median_ms(lambda: F.stream_copy(src, dst))
+    t_read = median_ms(lambda: F.stream_read(src, sink))
+    t_torch = median_ms(lambda: dst.copy_(src))
+    gbs = lambda nbytes, t: round(nbytes / (t * 1e-3) / 1e9, 1)  # noqa: E731
+    return {"gbs": gbs(2 * COPY_BYTES, t_copy), "read_gbs": gbs(COPY_BYTES, t_read),
+            "torch_copy_gbs": gbs(2 * COPY_BYTES, t_torch), "bytes": COPY_BYTES,
+            "kernels": "fmm_stream_copy (read + write), fmm_stream_read (read only), torch copy_"}
+
+
+def cold_cache_steps(step, reps, kinds, dev):
+    """The step timed with L2 and MALL flushed before each repetition (a 1 GiB scratch
+    buffer is overwritten between steps, outside the timed events)."""
+    import torch
+
+    scratch = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    per_step, per_kernel = [], {k: [] for k in kinds}
+    for i in range(reps):
+        scratch.fill_(float(i))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        step(ev)
+        torch.cuda.synchronize()
+        per_step.append(ev[0].elapsed_time(ev[3]))
+        for j, k in enumerate(kinds):
+            per_kernel[k].append(ev[j].elapsed_time(ev[j + 1]))
+    return {"median_ms": round(float(np.median(per_step)), 4), "reps": reps, "flush_bytes": COPY_BYTES,
+            "kernel_ms": {k: round(float(np.median(v)), 4) for k, v in per_kernel.items()}}
+
+
 def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
     """One step variant alone, for kernel traces and counter runs of that variant."""
     import torch
@@ -649,7 +703,7 @@ def main():
                 ev[3].record()
         return step
 
-    def time_steps(step, steps, warmup, per_kernel=True):
+    def time_steps(step, steps, warmup, per_kernel=True, step_ms=None):
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -663,6 +717,8 @@ def main():
         if per_kernel:
             ktimes = {k: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                       for i, k in enumerate(kinds)}
+            if step_ms is not None:
+                step_ms.extend(evs[s][0].elapsed_time(evs[s][3]) for s in range(steps))
         return t, ktimes
 
     flops = 12.0 * r * nnz
@@ -674,7 +730,8 @@ def main():
     log(f"autotuned (f32): {tuning}")
     step_f32 = make_step(A, B, fused=True)
     log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
-    t_step, kt = time_steps(step_f32, args.steps, args.warmup)
+    step_ms = []
+    t_step, kt = time_steps(step_f32, args.steps, args.warmup, step_ms=step_ms)
     gflops = flops / t_step / 1e9
     log(f"fused f32 step {t_step * 1e3:.3f} ms -> {gflops:.1f} GFLOP/s; kernels (ms) {kt}")
 
@@ -801,6 +858,19 @@ def main():
         tb = e0.elapsed_time(e1) / vsteps
         variants["fusedmm_b_step_fused_f32"] = {"ms_per_step": round(tb, 4), "gflops": round(flops / tb / 1e6, 1)}
         del Cb, Rb, Gb, dAb, dBb
+        # spread of the timed steps, then the same step with L2 and MALL flushed before each
+        variants["fused_f32_step_ms_percentiles"] = {
+            q: round(float(np.percentile(step_ms, p)), 4) for q, p in (("p10", 10), ("median", 50), ("p90", 90))}
+        cold = cold_cache_steps(step_f32, vsteps, kinds, dev)
+        variants["fused_f32_cold_cache"] = cold
+        log(f"cold-cache fused f32 step: median {cold['median_ms']:.3f} ms")
+        ceiling = copy_ceiling(dev)
+        roofline["copy_ceiling"] = ceiling
+        roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["gbs"], 4)
+        roofline["frac_of_read_ceiling"] = round(achieved / ceiling["read_gbs"], 4)
+        log(f"ceilings: copy {ceiling['gbs']:.0f} GB/s, read {ceiling['read_gbs']:.0f} GB/s, torch copy "
+            f"{ceiling['torch_copy_gbs']:.0f} GB/s; dominant kernel at {achieved / ceiling['gbs']:.3f} / "
+            f"{achieved / ceiling['read_gbs']:.3f} of them")
         variants["pattern_prep_s"] = round(prep_s, 3)
         variants["step_bytes_gather_model"] = int(step_bytes)
         variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)

@@ -136,6 +136,20 @@ int32_t fmm_last_hip_error(void);
 fmm_status fmm_device_info(int32_t *num_cu, char *arch, int32_t arch_len);
 
 /*
+ * Streaming probes for measurement (not part of the method): the HBM rate this GPU
+ * reaches on contiguous traffic, the practical ceiling next to the 8 TB/s specification
+ * against which the gather kernels' rates are read.
+ *   fmm_stream_copy: dst[0, bytes) = src[0, bytes)  (reads and writes `bytes` each)
+ *   fmm_stream_read: reads src[0, bytes) and folds it into one 32-bit value, which is
+ *                    stored to *sink only if it equals key (so the pass writes nothing
+ *                    in practice); sink: one device word.
+ * bytes: a multiple of 16 (else FMM_ERR_DIM); pointers 16-byte aligned (else
+ * FMM_ERR_UNSUPPORTED); the buffers must not overlap.  bytes = 0 does nothing.
+ */
+fmm_status fmm_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
+fmm_status fmm_stream_read(const void *src, size_t bytes, uint32_t key, uint32_t *sink, hipStream_t stream);
+
+/*
  * Lane-group shape override for every later launch in this process (tuning and
  * benchmarking): `lanes` lanes own one major line and each lane holds `nv` 16-byte
  * vectors of an r-vector.  (0, 0) restores the automatic choice (the smallest power of

@@ -34,6 +34,8 @@ from .fusedmm import (  # noqa: F401
     spmm_a_raw,
     spmm_b,
     spmm_b_raw,
+    stream_copy,
+    stream_read,
     to_bf16,
 )
 

@@ -27,7 +27,7 @@ from . import _capi as C
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
            "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "gat_backward", "gat",
            "gat_autotune", "cg_lines", "als_residual",
-           "als_sweep"]
+           "als_sweep", "stream_copy", "stream_read"]
 
 DEFAULT_LONG_LEN = 128
 DEFAULT_CHUNK = 128
@@ -922,6 +922,25 @@ def to_bf16(x: torch.Tensor) -> torch.Tensor:
     y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
     C.call("fmm_f32_to_bf16", _ptr(x), _ptr(y), x.numel(), _stream())
     return y
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor):
+    """Streaming probe: copy src's bytes into dst with the library's plain copy kernel
+    (the measured HBM ceiling for read + write traffic)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("stream_copy takes contiguous GPU tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    C.call("fmm_stream_copy", _ptr(src), _ptr(dst), nbytes, _stream())
+
+
+def stream_read(src: torch.Tensor, sink: torch.Tensor, key: int = 0x9E3779B9):
+    """Streaming probe: read every byte of src (the measured HBM ceiling for read-only
+    traffic); sink is one int32 device word, written only if the folded value equals key."""
+    if not (src.is_cuda and sink.is_cuda and src.is_contiguous()) or sink.dtype != torch.int32 or sink.numel() < 1:
+        raise ValueError("stream_read takes a contiguous GPU tensor and a one-word int32 GPU sink")
+    C.call("fmm_stream_read", _ptr(src), src.numel() * src.element_size(), key, _ptr(sink), _stream())
 
 
 def set_tuning(lanes: int = 0, nv: int = 0):

@@ -225,3 +225,14 @@ def test_gat_backward_argument_errors():
     assert call(ws=FAKE + 16) == -7                              # workspace is 256-byte aligned
     assert call(r=12, dtype=1) == -3                             # bf16 needs r % 8 == 0
     assert call(lse=None) == -1                                  # the softmax adjoint needs the forward's lse
+
+
+def test_stream_probe_argument_errors():
+    lib = C.load()
+    assert lib.fmm_stream_copy(FAKE, FAKE, 0, None) == 0       # nothing to do
+    assert lib.fmm_stream_copy(None, FAKE, 64, None) == -1
+    assert lib.fmm_stream_copy(FAKE, FAKE, 60, None) == -2     # not a multiple of 16
+    assert lib.fmm_stream_copy(FAKE + 4, FAKE, 64, None) == -8  # misaligned
+    assert lib.fmm_stream_read(FAKE, 64, 0, None, None) == -1
+    assert lib.fmm_stream_read(FAKE, 24, 0, FAKE, None) == -2
+    assert lib.fmm_stream_read(FAKE + 8, 64, 0, FAKE, None) == -8
