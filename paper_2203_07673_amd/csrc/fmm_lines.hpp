@@ -90,65 +90,141 @@ struct LineArgs {
 __device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
 
+// Streaming (nontemporal) cache hint for data a pass touches once, so that it does not
+// displace gathered rows (the only reused data) from L2 and the MALL.  On by default for
+// the held rows (one 16-byte load per lane per line) and the row outputs.  Off for the
+// index and weight arrays: they are read with one dword load per entry, and the lines
+// that consecutive batches share would be refetched.  Off for the gathered rows, whose
+// reuse is the point of the cache.  Every setting gives the same results.
+#ifndef FMM_NT_META
+#define FMM_NT_META 0
+#endif
+#ifndef FMM_NT_HELD
+#define FMM_NT_HELD 1
+#endif
+#ifndef FMM_NT_STORE
+#define FMM_NT_STORE 1
+#endif
+#ifndef FMM_NT_GATHER
+#define FMM_NT_GATHER 0
+#endif
+constexpr bool kNtMeta = FMM_NT_META != 0;
+constexpr bool kNtHeld = FMM_NT_HELD != 0;
+constexpr bool kNtStore = FMM_NT_STORE != 0;
+constexpr bool kNtGather = FMM_NT_GATHER != 0;
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+template <bool NT, class V> __device__ __forceinline__ V ld_hint(const V *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class V> __device__ __forceinline__ void st_hint(V *p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Load VW consecutive elements of T at p (16-byte vector loads where VW*sizeof(T)
-// is a multiple of 16) and widen them to Acc.
+// is a multiple of 16) and widen them to Acc; NT: with the streaming hint.
 template <class T, int VW, class Acc> struct Ld;
 
 template <> struct Ld<float, 1, float> {
-    static __device__ __forceinline__ void run(const float *p, float *o) { o[0] = p[0]; }
+    template <bool NT = false> static __device__ __forceinline__ void run(const float *p, float *o) {
+        o[0] = ld_hint<NT>(p);
+    }
 };
 template <> struct Ld<float, 4, float> {
-    static __device__ __forceinline__ void run(const float *p, float *o) {
-        float4 v = *reinterpret_cast<const float4 *>(p);
-        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    template <bool NT = false> static __device__ __forceinline__ void run(const float *p, float *o) {
+        if constexpr (NT) {
+            const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+            o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+        } else {
+            float4 v = *reinterpret_cast<const float4 *>(p);
+            o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+        }
     }
 };
 template <> struct Ld<float, 8, float> {
-    static __device__ __forceinline__ void run(const float *p, float *o) {
-        float4 v = reinterpret_cast<const float4 *>(p)[0];
-        float4 w = reinterpret_cast<const float4 *>(p)[1];
-        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-        o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+    template <bool NT = false> static __device__ __forceinline__ void run(const float *p, float *o) {
+        if constexpr (NT) {
+            const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+            const f32x4_t w = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p) + 1);
+            o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+        } else {
+            float4 v = reinterpret_cast<const float4 *>(p)[0];
+            float4 w = reinterpret_cast<const float4 *>(p)[1];
+            o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+        }
     }
 };
 template <> struct Ld<bf16_t, 8, float> {
-    static __device__ __forceinline__ void run(const bf16_t *p, float *o) {
-        uint4 v = *reinterpret_cast<const uint4 *>(p);
-        o[0] = bf16_lo(v.x); o[1] = bf16_hi(v.x); o[2] = bf16_lo(v.y); o[3] = bf16_hi(v.y);
-        o[4] = bf16_lo(v.z); o[5] = bf16_hi(v.z); o[6] = bf16_lo(v.w); o[7] = bf16_hi(v.w);
+    template <bool NT = false> static __device__ __forceinline__ void run(const bf16_t *p, float *o) {
+        if constexpr (NT) {
+            const u32x4_t v = ld_hint<true>(reinterpret_cast<const u32x4_t *>(p));
+            o[0] = bf16_lo(v.x); o[1] = bf16_hi(v.x); o[2] = bf16_lo(v.y); o[3] = bf16_hi(v.y);
+            o[4] = bf16_lo(v.z); o[5] = bf16_hi(v.z); o[6] = bf16_lo(v.w); o[7] = bf16_hi(v.w);
+        } else {
+            uint4 v = *reinterpret_cast<const uint4 *>(p);
+            o[0] = bf16_lo(v.x); o[1] = bf16_hi(v.x); o[2] = bf16_lo(v.y); o[3] = bf16_hi(v.y);
+            o[4] = bf16_lo(v.z); o[5] = bf16_hi(v.z); o[6] = bf16_lo(v.w); o[7] = bf16_hi(v.w);
+        }
     }
 };
 template <> struct Ld<double, 1, double> {
-    static __device__ __forceinline__ void run(const double *p, double *o) { o[0] = p[0]; }
+    template <bool NT = false> static __device__ __forceinline__ void run(const double *p, double *o) {
+        o[0] = ld_hint<NT>(p);
+    }
 };
 template <> struct Ld<double, 2, double> {
-    static __device__ __forceinline__ void run(const double *p, double *o) {
-        double2 v = *reinterpret_cast<const double2 *>(p);
-        o[0] = v.x; o[1] = v.y;
+    template <bool NT = false> static __device__ __forceinline__ void run(const double *p, double *o) {
+        if constexpr (NT) {
+            const f64x2_t v = ld_hint<true>(reinterpret_cast<const f64x2_t *>(p));
+            o[0] = v.x; o[1] = v.y;
+        } else {
+            double2 v = *reinterpret_cast<const double2 *>(p);
+            o[0] = v.x; o[1] = v.y;
+        }
     }
 };
 
 template <class Acc, int VW> struct St;
 template <> struct St<float, 1> {
-    static __device__ __forceinline__ void run(float *p, const float *v) { p[0] = v[0]; }
+    template <bool NT = false> static __device__ __forceinline__ void run(float *p, const float *v) {
+        st_hint<NT>(p, v[0]);
+    }
 };
 template <> struct St<float, 4> {
-    static __device__ __forceinline__ void run(float *p, const float *v) {
-        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    template <bool NT = false> static __device__ __forceinline__ void run(float *p, const float *v) {
+        if constexpr (NT) st_hint<true>(reinterpret_cast<f32x4_t *>(p), f32x4_t{v[0], v[1], v[2], v[3]});
+        else *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
     }
 };
 template <> struct St<float, 8> {
-    static __device__ __forceinline__ void run(float *p, const float *v) {
-        reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
-        reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+    template <bool NT = false> static __device__ __forceinline__ void run(float *p, const float *v) {
+        if constexpr (NT) {
+            st_hint<true>(reinterpret_cast<f32x4_t *>(p), f32x4_t{v[0], v[1], v[2], v[3]});
+            st_hint<true>(reinterpret_cast<f32x4_t *>(p) + 1, f32x4_t{v[4], v[5], v[6], v[7]});
+        } else {
+            reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+            reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+        }
     }
 };
 template <> struct St<double, 1> {
-    static __device__ __forceinline__ void run(double *p, const double *v) { p[0] = v[0]; }
+    template <bool NT = false> static __device__ __forceinline__ void run(double *p, const double *v) {
+        st_hint<NT>(p, v[0]);
+    }
 };
 template <> struct St<double, 2> {
-    static __device__ __forceinline__ void run(double *p, const double *v) {
-        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    template <bool NT = false> static __device__ __forceinline__ void run(double *p, const double *v) {
+        if constexpr (NT) st_hint<true>(reinterpret_cast<f64x2_t *>(p), f64x2_t{v[0], v[1]});
+        else *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
     }
 };
 
@@ -158,7 +234,7 @@ template <class T, int VW> struct Raw;
 template <> struct Raw<float, 1> {
     float x;
     __device__ __forceinline__ void pin() {}
-    __device__ __forceinline__ void load(const float *p) { x = p[0]; }
+    __device__ __forceinline__ void load(const float *p) { x = ld_hint<kNtGather>(p); }
     __device__ __forceinline__ void zero() { x = 0.f; }
     __device__ __forceinline__ float get(int) const { return x; }
 };
@@ -166,7 +242,12 @@ template <> struct Raw<float, 4> {
     float4 x;
     __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) {
-        x = *reinterpret_cast<const float4 *>(p);
+        if constexpr (kNtGather) {
+            const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+            x = make_float4(v.x, v.y, v.z, v.w);
+        } else {
+            x = *reinterpret_cast<const float4 *>(p);
+        }
     }
     __device__ __forceinline__ void zero() { x = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
@@ -175,8 +256,15 @@ template <> struct Raw<float, 8> {
     float4 x, y;
     __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) {
-        x = reinterpret_cast<const float4 *>(p)[0];
-        y = reinterpret_cast<const float4 *>(p)[1];
+        if constexpr (kNtGather) {
+            const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+            const f32x4_t w = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p) + 1);
+            x = make_float4(v.x, v.y, v.z, v.w);
+            y = make_float4(w.x, w.y, w.z, w.w);
+        } else {
+            x = reinterpret_cast<const float4 *>(p)[0];
+            y = reinterpret_cast<const float4 *>(p)[1];
+        }
     }
     __device__ __forceinline__ void zero() { x = y = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const {
@@ -188,7 +276,12 @@ template <> struct Raw<float, 8> {
 template <> struct Raw<bf16_t, 8> {
     uint4 x;
     __device__ __forceinline__ void load(const bf16_t *p) {
-        x = *reinterpret_cast<const uint4 *>(p);
+        if constexpr (kNtGather) {
+            const u32x4_t v = ld_hint<true>(reinterpret_cast<const u32x4_t *>(p));
+            x = make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+            x = *reinterpret_cast<const uint4 *>(p);
+        }
     }
     __device__ __forceinline__ void zero() { x = make_uint4(0u, 0u, 0u, 0u); }
     // Make the packed words opaque to the optimiser, so elements widened for the dot
@@ -429,7 +522,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (act[v]) {
-                Ld<TH, VW, Acc>::run(Hrow + off[v], h + v * VW);
+                Ld<TH, VW, Acc>::template run<kNtHeld>(Hrow + off[v], h + v * VW);
             } else {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) h[v * VW + e] = Acc(0);
@@ -443,7 +536,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (act[v]) {
-                Ld<TG2, VW, Acc>::run(H2row + off[v], h2 + v * VW);
+                Ld<TG2, VW, Acc>::template run<kNtHeld>(H2row + off[v], h2 + v * VW);
             } else {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) h2[v * VW + e] = Acc(0);
@@ -476,8 +569,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
             const int32_t pc = (FULL || p < end) ? p : end - 1;
-            j[u] = idx[pc];
-            const Acc base = val_p[pc * vs];
+            j[u] = ld_hint<kNtMeta>(idx + pc);
+            const Acc base = ld_hint<kNtMeta>(val_p + pc * vs);
             if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
                 const int32_t q = perm_p[pc * ps] + pc * (1 - ps);
                 w1[u] = base * wv1_p[q * w1s];
@@ -688,7 +781,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
                     for (int e = 0; e < VW; ++e) outv[e] = acc[v * VW + e];
                 }
-                St<Acc, VW>::run(dst + off[v], outv);
+                St<Acc, VW>::template run<kNtStore>(dst + off[v], outv);
             }
         }
     }
