@@ -54,8 +54,9 @@ def kernel_bytes_min(kind, m, n, nnz, r, e):
     raise ValueError(kind)
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload."""
+def cpu_baseline(w, target_s=15.0, single_s=6.0):
+    """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload, with all
+    of the host's threads (the reported value) and with one thread."""
     from types import SimpleNamespace
 
     import oracle
@@ -75,16 +76,27 @@ def cpu_baseline(w, target_s=15.0):
         oracle.fusedmm_a_backward(Sk, A[:K], B, G[:K])
         return time.perf_counter() - t0, nz
 
-    # grow the row sample until the timed run takes at least half the target time
-    K = min(S.m, 8192)
-    t, nz = run(K)
-    while t < 0.5 * target_s and K < S.m:
-        K = int(min(S.m, max(2 * K, K * target_s / max(t, 1e-3))))
+    def sample(K, target):
+        # grow the row sample until the timed run takes at least half the target time
         t, nz = run(K)
+        while t < 0.5 * target and K < S.m:
+            K = int(min(S.m, max(2 * K, K * target / max(t, 1e-3))))
+            t, nz = run(K)
+        return K, t, nz
+
+    threads = oracle.num_threads()
+    K, t, nz = sample(min(S.m, 8192), target_s)
+    oracle.set_num_threads(1)
+    try:
+        K1, t1, nz1 = sample(min(S.m, 1024), single_s)
+    finally:
+        oracle.set_num_threads(threads)
     gflops = 12.0 * r * nz / t / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"first {K} of {S.m} rows ({nz} nonzeros), FusedMMA forward + adjoint in float64, "
-                      f"{t:.1f} s"}
+                      f"{t:.1f} s, one run",
+            "single_thread": {"value": round(12.0 * r * nz1 / t1 / 1e9, 3), "cores": 1,
+                              "sample": f"first {K1} rows ({nz1} nonzeros), {t1:.1f} s, one run"}}
 
 COPY_BYTES = 1 << 30
 # the sources that define the line kernels (their counters go stale when these change)
@@ -615,8 +627,8 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="er1m_d32_r128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -673,6 +685,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # every launch and timing event of the bench goes to one dedicated stream
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))
     t_prep = time.perf_counter()
     P = F.Pattern.from_csr(S, device=dev)
     torch.cuda.synchronize()

@@ -58,6 +58,8 @@ def _load():
             lib.oracle_spmm_b.argtypes = [i64, i64, i64, p, p, p, p, p]
             lib.oracle_csr_to_csc.argtypes = [i64, i64, p, p, p, p, p, p, p]
             lib.oracle_num_threads.restype = ctypes.c_int
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_threads.restype = None
             lib.oracle_gat_scores.argtypes = [i64, i64, p, p, p, p, p]
             lib.oracle_gat_scores.restype = None
             lib.oracle_gat_edges.argtypes = [i64, p, p, p, p, p, ctypes.c_double, ctypes.c_int, p]
@@ -86,6 +88,11 @@ def _rows(rows):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the OpenMP routines (timing at a fixed thread count)."""
+    _load().oracle_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------------

@@ -132,6 +132,17 @@ void oracle_csr_to_csc(int64_t m, int64_t n, const int32_t *rowptr, const int32_
     free(next);
 }
 
+/* Threads for the routines above (n >= 1; for timing at a fixed thread count). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads the routines above use (for reporting). */
 int oracle_num_threads(void)
 {
