@@ -102,15 +102,21 @@ COPY_BYTES = 1 << 30
 # the sources that define the line kernels (their counters go stale when these change)
 SRC_GLOBS = ("paper_2203_07673_amd/csrc/fmm_lines.hpp", "paper_2203_07673_amd/csrc/fmm_launch.hpp",
              "paper_2203_07673_amd/csrc/lines_*.hip")
+# and those of the batched persistent kernel, which runs the same per-line body
+BATCH_SRC_GLOBS = SRC_GLOBS + ("paper_2203_07673_amd/csrc/batch*.hip", "paper_2203_07673_amd/csrc/batch_kernels.hpp")
 
 
-def source_hash():
+def source_globs(workload_name):
+    return BATCH_SRC_GLOBS if workload_name.startswith("batch") else SRC_GLOBS
+
+
+def source_hash(globs=SRC_GLOBS):
     """SHA-256 over the HIP sources: counter data is valid only for the kernels it measured."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
-    for pat in SRC_GLOBS:
+    for pat in globs:
         for f in sorted(glob.glob(os.path.join(ROOT, pat))):
             h.update(os.path.basename(f).encode())
             with open(f, "rb") as fh:
@@ -146,7 +152,7 @@ def calibration_dispatches(per):
     return sorted(i for i, v in copies.items() if top > 0 and abs(v - top) < 0.01 * top)
 
 
-def pmc_summary(fetch_dir, write_dir, out_json, command=""):
+def pmc_summary(fetch_dir, write_dir, out_json, command="", workload_name=None, tuned=""):
     """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from two counter runs of the
     same command, with scale factors from the plain device copy of COPY_BYTES bytes that
     --calibrate-copy ran.  The copies are found in each run on its own, as its largest
@@ -181,8 +187,10 @@ def pmc_summary(fetch_dir, write_dir, out_json, command=""):
     for k, v in kernels.items():
         summary[k] = {c: sum(x) / len(x) for c, x in v.items()}
         summary[k]["dispatches"] = max(len(x) for x in v.values())
-    out = {"command": command, "source_hash": source_hash(), "copy_bytes": COPY_BYTES,
-           "copy_dispatches": {c: sorted(v) for c, v in calib.items()}, "scale": scale,
+    if workload_name is None:  # traffic_<workload>.json
+        workload_name = os.path.basename(out_json)[len("traffic_"):].rsplit(".", 1)[0]
+    out = {"command": command, "source_hash": source_hash(source_globs(workload_name)), "copy_bytes": COPY_BYTES,
+           "copy_dispatches": {c: sorted(v) for c, v in calib.items()}, "scale": scale, "tuned_arg": tuned,
            "note": "KiB per dispatch as the counters read them; bytes = (FETCH*scale_f + WRITE*scale_w)*1024",
            "kernels": summary}
     with open(out_json, "w") as fh:
@@ -199,6 +207,8 @@ def _role(key):
         return ROLES.get(int(key[len("line_kernel<"):].split(",", 1)[0]), "line kernel")
     if "merge_kernel" in key:
         return "split-line merge"
+    if "batch_kernel<" in key:
+        return "batched persistent (all passes of every graph)"
     if "f32_to_bf16" in key:
         return "bf16 rounding of A, B"
     return None
@@ -289,7 +299,7 @@ def load_traffic(workload_name, kernel_key):
         return None
     with open(f) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash(source_globs(workload_name)):
         return None
     k = t["kernels"].get(kernel_key)
     sf, sw = t["scale"].get("FETCH_SIZE"), t["scale"].get("WRITE_SIZE")
@@ -322,8 +332,15 @@ def run_batch(args):
     A = [F.to_bf16(a) for a in A32]
     B = [F.to_bf16(b) for b in B32]
     plan = F.BatchPlan(pats, A, B, G)
-    info = plan.autotune()
-    log(f"autotuned: {info}")
+    if args.tuned:  # TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE, as a bench run's autotune chose it
+        tile, xcd, roww, colw = (int(x) for x in args.tuned.split(":"))
+        plan.set_schedule(tile, bool(xcd), bool(roww), bool(colw))
+        info = plan.info()
+        log(f"schedule from --tuned: {info}")
+    else:
+        info = plan.autotune()
+        log(f"autotuned: {info}")
+    tuned_arg = f"{info['tile_nnz']}:{info['xcd_aware']}:{info['row_schedule']}:{info['col_schedule']}"
     side = torch.cuda.Stream()
     plan.capture(side)
     with torch.cuda.stream(side):
@@ -350,6 +367,20 @@ def run_batch(args):
         for kind in ("fwd", "bwd_row", "bwd_col"):
             bytes_launch += kernel_bytes(kind, S.m, S.n, S.nnz, r, e)
     achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    # counter-measured bytes per launch of the chosen schedule's kernel, when the committed
+    # counter summary covers the current sources
+    waves = 64 // info["lanes"]  # line groups sharing a wavefront in the wavefront-per-line schedule
+    kernel_key = (f"void fmm::batch_kernel<unsigned short, {info['lanes']}, 8, "
+                  f"{waves if info['row_schedule'] else 1}, {waves if info['col_schedule'] else 1}>")
+    traffic = None
+    f = os.path.join(ROOT, "profiles", "traffic_batch256_r64.json")
+    if os.path.exists(f):
+        with open(f) as fh:
+            t = json.load(fh)
+        k = next((v for kk, v in t["kernels"].items() if kk.startswith(kernel_key)), None)
+        if (t.get("source_hash") == source_hash(BATCH_SRC_GLOBS) and k and t["scale"]["FETCH_SIZE"]
+                and t.get("tuned_arg") == tuned_arg):
+            traffic = (k["FETCH_SIZE"] * t["scale"]["FETCH_SIZE"] + k["WRITE_SIZE"] * t["scale"]["WRITE_SIZE"]) * 1024.0
 
     variants = {"autotune": info}
     if not args.no_variants:
@@ -384,14 +415,20 @@ def run_batch(args):
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch256_r64", "graphs": 256, "rows": rows, "nnz": nnz, "r": r, "storage": "bf16",
                    "step": "hipGraph replay of one persistent launch: fused forward + adjoint of every graph",
-                   "flops_per_step": flops},
+                   "flops_per_step": flops, "tuning_arg": tuned_arg},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "batch_kernel (persistent, all passes)", "kernel_ms": round(k_ms, 4),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else int(traffic),
+                     "traffic_gbs": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9, 1),
+                     "traffic_frac": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "kernel": f"batch_kernel (persistent, all passes): {kernel_key}", "kernel_ms": round(k_ms, 4),
                      "bytes_per_launch": int(bytes_launch),
-                     "bytes_model": "gather; graphs' B are L2/MALL-sized, so HBM is not the binding limit"},
+                     "bytes_model": "gather (each stored entry fetches its dense rows); rows that hit in L2 make "
+                                    "the counter traffic smaller"},
         "variants": variants,
     }
+    if args.calibrate_copy:
+        calibrate_copy(dev)
     print(json.dumps(out), flush=True)
 
 
@@ -645,11 +682,12 @@ def main():
                          "threshold come from --tuned, else the defaults)")
     ap.add_argument("--tuned", default="",
                     help="csr=VARIANT:LONG_LEN:ORDER,csc=VARIANT:LONG_LEN:ORDER as a bench run's autotune chose "
-                         "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1)")
+                         "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1); for batch256_r64 "
+                         "TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, command=args.command)
+        pmc_summary(*args.pmc_summary, command=args.command, tuned=args.tuned)
         return
     if args.trace_summary:
         trace_summary(*args.trace_summary, command=args.command)
