@@ -34,7 +34,8 @@ def test_committed_counter_summaries_parse():
             t = json.load(open(os.path.join(ROOT, "profiles", f)))
             assert t["scale"]["FETCH_SIZE"] and t["scale"]["WRITE_SIZE"]
             assert t["command"].startswith("rocprofv3")
-            assert any(k.startswith("line_kernel<") for k in t["kernels"])
+            kernel = "batch_kernel<" if f.startswith("traffic_batch") else "line_kernel<"
+            assert any(kernel in k for k in t["kernels"])
 
 
 def _write_pmc(d, counter, rows):
