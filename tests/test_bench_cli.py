@@ -51,10 +51,11 @@ def test_counter_calibration_when_the_runs_number_dispatches_differently(tmp_pat
     calibration copies are found in each run by themselves and scale each counter."""
     kib = bench.COPY_BYTES / 1024.0
     lk = "void fmm::line_kernel<3, float, float, float, float, 32, 1, 4, 2>(fmm::LineArgs)"
-    fetch = [(1, "__amd_rocclr_copyBuffer", 2.0), (2, lk, 100.0), (3, lk, 100.0)] + \
+    probe = "fmm::(anonymous namespace)::stream_copy_kernel(HIP_vector_type<unsigned int, 4u> const*)"
+    fetch = [(1, "__amd_rocclr_copyBuffer", 2.0), (2, lk, 100.0), (3, lk, 100.0), (4, probe, 2 * kib)] + \
         [(10 + i, "__amd_rocclr_copyBuffer", kib / 2) for i in range(3)]
-    write = [(1, "__amd_rocclr_copyBuffer", 4.0), (2, lk, 30.0), (3, lk, 30.0), (4, lk, 30.0), (5, lk, 30.0)] + \
-        [(20 + i, "__amd_rocclr_copyBuffer", kib) for i in range(3)]
+    write = [(1, "__amd_rocclr_copyBuffer", 4.0), (2, lk, 30.0), (3, lk, 30.0), (4, lk, 30.0), (5, lk, 30.0),
+             (6, probe, 4 * kib)] + [(20 + i, "__amd_rocclr_copyBuffer", kib) for i in range(3)]
     _write_pmc(str(tmp_path / "f"), "FETCH_SIZE", fetch)
     _write_pmc(str(tmp_path / "w"), "WRITE_SIZE", write)
     out = str(tmp_path / "t.json")
@@ -64,7 +65,7 @@ def test_counter_calibration_when_the_runs_number_dispatches_differently(tmp_pat
     assert t["copy_dispatches"] == {"FETCH_SIZE": [10, 11, 12], "WRITE_SIZE": [20, 21, 22]}
     k = t["kernels"]["line_kernel<3, float, float, float, float, 32, 1, 4, 2>"]
     assert k["FETCH_SIZE"] == 100.0 and k["WRITE_SIZE"] == 30.0 and k["dispatches"] == 4
-    # a write run whose largest copy is not the calibration size gives no scale at all
-    _write_pmc(str(tmp_path / "w2"), "WRITE_SIZE", write[:5])
+    # a write run whose largest runtime copy is not the calibration size gives no scale
+    _write_pmc(str(tmp_path / "w2"), "WRITE_SIZE", write[:6])
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w2"), out)
     assert json.load(open(out))["scale"] == {"FETCH_SIZE": None, "WRITE_SIZE": None}
