@@ -3,8 +3,9 @@
 Rows of FusedMMA (and columns of FusedMMB) are independent, so checking a seeded
 sample of them against the oracle is exact for those outputs.  Samples include the
 longest lines (the split-chunk path on R-MAT), empty lines and random ones.  Calls
-run in the same launch configuration the benchmark times (default shapes, the
-Pattern's automatic split schedule).
+run in the Pattern's default configuration (default shapes and split schedule);
+test_gpu_tuning_full.py repeats the check under every configuration the benchmark's
+autotuner can choose.
 """
 import numpy as np
 import pytest
