@@ -842,9 +842,31 @@ def main():
         variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
                                   "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()},
                                   "tuning_arg": tuning_arg(P.tuning)}
-        restore_tuning(P, tuning)
         log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
+
+        # bfloat16 upstream gradient as well: the step rounds G to bfloat16 (inside the
+        # timed step) and both adjoint passes read it as stored
+        def step_dc16(ev=None):
+            if ev is not None:
+                ev[0].record()
+            F.fusedmm_a_raw(P, A16, B16, out=C)
+            if ev is not None:
+                ev[1].record()
+            G16 = F.to_bf16(G)
+            F.fusedmm_a_backward_raw(P, A16, B16, G16, dA=dA, need=(True, False))
+            if ev is not None:
+                ev[2].record()
+            F.fusedmm_a_backward_raw(P, A16, B16, G16, dB=dB, need=(False, True))
+            if ev is not None:
+                ev[3].record()
+        t_bg, kt_bg = time_steps(step_dc16, vsteps, 2)
+        variants["fused_bf16_dc_bf16"] = {"ms_per_step": round(t_bg * 1e3, 4), "gflops": round(flops / t_bg / 1e9, 1),
+                                          "kernel_ms": {k: round(v, 4) for k, v in kt_bg.items()},
+                                          "note": "dC rounded to bfloat16 in the step (in the bwd_row time)"}
+        log(f"fused bf16 step with a bf16 upstream gradient {t_bg * 1e3:.3f} ms")
+        restore_tuning(P, tuning)
         variants["speedup_fused_bf16_vs_unfused_f32"] = round(t_unf / t_bf, 3)
+        variants["speedup_fused_bf16_dc_bf16_vs_unfused_f32"] = round(t_unf / t_bg, 3)
         variants["speedup_fused_f32_vs_unfused_f32"] = round(t_unf / t_step, 3)
         del A16, B16
         # learned edge values: the adjoint also returns dL/dS; fused, dS is written by the

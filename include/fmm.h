@@ -78,6 +78,7 @@ typedef enum fmm_orient { FMM_CSR = 0, FMM_CSC = 1 } fmm_orient;
 /* flags for the fused calls */
 #define FMM_FUSED 0    /* one pass, sampled values kept in registers                    */
 #define FMM_UNFUSED 1  /* SDDMM writes R (nnz values) to R_ws, then SpMM reads it back  */
+#define FMM_DC_BF16 2  /* adjoints only, OR-ed with FMM_FUSED: dC is bfloat16 storage    */
 
 /*
  * A sparse matrix S (rows x cols) in one orientation.
@@ -328,6 +329,10 @@ fmm_status fmm_autotune(int32_t op, fmm_sparse *S_csr, fmm_sparse *S_csc, const 
  * dA or dB may be NULL to skip that output.  FMM_FUSED recomputes the sampled values
  * in registers; FMM_UNFUSED writes dP to dP_ws (nnz, CSR order) and needs R from the
  * unfused forward in R_ws (CSR order) plus S_csc->perm.
+ * FMM_FUSED | FMM_DC_BF16 (dtype FMM_BF16 only, else FMM_ERR_UNSUPPORTED): dC is
+ * stored as bfloat16 like A and B, so the column pass gathers 2 bytes per element of
+ * dC instead of 4 (accumulation and outputs stay float32).  The rounding of dC is the
+ * caller's: results are those for the rounded dC.
  */
 fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
                                   const void *B, const void *dC, int32_t r, int32_t dtype,
@@ -339,8 +344,8 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
  *   dP = S * (A dC^T)
  *   dA = dP B + R dC           (row pass on S_csr)
  *   dB = dP^T A                = FusedMMB(S, A, dC)            (column pass on S_csc)
- * Same flag and workspace rules as fmm_fusedmm_a_backward (R_ws, from the unfused
- * FusedMMB forward, and dP_ws are both in CSR order).
+ * Same flag and workspace rules as fmm_fusedmm_a_backward, FMM_DC_BF16 included (R_ws,
+ * from the unfused FusedMMB forward, and dP_ws are both in CSR order).
  */
 fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
                                   const void *B, const void *dC, int32_t r, int32_t dtype,

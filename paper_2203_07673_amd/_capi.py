@@ -19,6 +19,7 @@ FMM_OK = 0
 FMM_F32, FMM_BF16, FMM_F64 = 0, 1, 2
 FMM_CSR, FMM_CSC = 0, 1
 FMM_FUSED, FMM_UNFUSED = 0, 1
+FMM_DC_BF16 = 2
 FMM_VARIANT_AUTO, FMM_VARIANT_DEEP, FMM_VARIANT_MEDIUM, FMM_VARIANT_SHALLOW = 0, 1, 2, 3
 (FMM_OP_SDDMM, FMM_OP_SPMM_A, FMM_OP_SPMM_B, FMM_OP_FUSEDMM_A, FMM_OP_FUSEDMM_B, FMM_OP_FUSEDMM_A_BWD,
  FMM_OP_FUSEDMM_B_BWD, FMM_OP_SDDMM_BWD, FMM_OP_SPMM_A_BWD, FMM_OP_SPMM_B_BWD,

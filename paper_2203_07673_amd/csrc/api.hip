@@ -179,6 +179,7 @@ hipError_t run(int path, char hk, char g1k, char g2k, const LineArgs &a, const f
         if (hk == 'O' && g1k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
     } else if constexpr (OP == OP_FUSED2) {
         if (hk == 'S' && g1k == 'S' && g2k == 'O') return launch_lines<OP, Sb, Sb, Of, float>(a, ns, sp, hint(), st);
+        if (hk == 'S' && g1k == 'S' && g2k == 'S') return launch_lines<OP, Sb, Sb, Sb, float>(a, ns, sp, hint(), st);
     } else if constexpr (OP == OP_FUSED1S) {  // g2k: kind of the second held row
         if (hk == 'O' && g1k == 'S' && g2k == 'S') return launch_lines<OP, Of, Sb, Sb, float>(a, ns, sp, hint(), st);
     }
@@ -638,13 +639,17 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
     Kinds k;
     FMM_TRY(kinds_for(dtype, r, &k));
     const int32_t m = S_csr->rows, n = S_csr->cols;
+    const bool dc16 = (flags & FMM_DC_BF16) != 0;
+    flags &= ~FMM_DC_BF16;
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (dc16 && (dtype != FMM_BF16 || flags != FMM_FUSED)) return FMM_ERR_UNSUPPORTED;
+    const char dck = dc16 ? 'S' : 'O';  // kind of dC: bfloat16 storage or float32
     FMM_TRY(check_dense(A, m, k.sbytes, r));
     FMM_TRY(check_dense(B, n, k.sbytes, r));
-    FMM_TRY(check_dense(dC, m, k.obytes, r));
+    FMM_TRY(check_dense(dC, m, dc16 ? k.sbytes : k.obytes, r));
     if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
     if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
     FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
-    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
     if (flags == FMM_UNFUSED) {
         if (S_csr->nnz > 0 && (!dP_ws || (dB && (!R_ws || !S_csc->perm)))) return FMM_ERR_WORKSPACE;
         LineArgs s = base_args(S_csr, r, nullptr);  // dP = S * (dC B^T)
@@ -680,7 +685,7 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
         a.H = dC;
         a.G1 = B;
         a.out = dA;
-        FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S_csr, stream));
+        FMM_HIP(run<OP_FUSED1>(k.path, dck, 'S', 'S', a, S_csr, stream));
     }
     if (dB) {  // dB_j = sum_i S_ij (<B_j, dC_i> A_i + <B_j, A_i> dC_i)
         LineArgs a = base_args(S_csc, r, ws);
@@ -688,7 +693,7 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
         a.G1 = A;
         a.G2 = dC;
         a.out = dB;
-        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', 'O', a, S_csc, stream));
+        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', dck, a, S_csc, stream));
     }
     return FMM_OK;
 }
@@ -701,13 +706,17 @@ fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
     Kinds k;
     FMM_TRY(kinds_for(dtype, r, &k));
     const int32_t m = S_csr->rows, n = S_csr->cols;
+    const bool dc16 = (flags & FMM_DC_BF16) != 0;
+    flags &= ~FMM_DC_BF16;
+    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
+    if (dc16 && (dtype != FMM_BF16 || flags != FMM_FUSED)) return FMM_ERR_UNSUPPORTED;
+    const char dck = dc16 ? 'S' : 'O';
     FMM_TRY(check_dense(A, m, k.sbytes, r));
     FMM_TRY(check_dense(B, n, k.sbytes, r));
-    FMM_TRY(check_dense(dC, n, k.obytes, r));
+    FMM_TRY(check_dense(dC, n, dc16 ? k.sbytes : k.obytes, r));
     if (dA) FMM_TRY(check_dense(dA, m, k.obytes, r));
     if (dB) FMM_TRY(check_dense(dB, n, k.obytes, r));
     FMM_TRY(check_ws2(S_csr, S_csc, r, k.obytes, ws, ws_bytes));
-    if (flags != FMM_FUSED && flags != FMM_UNFUSED) return FMM_ERR_DIM;
     if (flags == FMM_UNFUSED) {
         if (S_csr->nnz > 0 && (!dP_ws || (dA && !R_ws) || (dB && !S_csc->perm))) return FMM_ERR_WORKSPACE;
         LineArgs s = base_args(S_csr, r, nullptr);  // dP = S * (A dC^T), CSR order
@@ -743,7 +752,7 @@ fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
         a.H = dC;
         a.G1 = A;
         a.out = dB;
-        FMM_HIP(run<OP_FUSED1>(k.path, 'O', 'S', 'S', a, S_csc, stream));
+        FMM_HIP(run<OP_FUSED1>(k.path, dck, 'S', 'S', a, S_csc, stream));
     }
     if (dA) {  // dA_i = sum_j S_ij (<A_i, dC_j> B_j + <A_i, B_j> dC_j)
         LineArgs a = base_args(S_csr, r, ws);
@@ -751,7 +760,7 @@ fmm_status fmm_fusedmm_b_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
         a.G1 = B;
         a.G2 = dC;
         a.out = dA;
-        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', 'O', a, S_csr, stream));
+        FMM_HIP(run<OP_FUSED2>(k.path, 'S', 'S', dck, a, S_csr, stream));
     }
     return FMM_OK;
 }

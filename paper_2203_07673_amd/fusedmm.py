@@ -427,12 +427,26 @@ def fusedmm_b_raw(P, A, B, out=None, fused=True, R_ws=None):
     return out, R_ws
 
 
+def _dc_flag(dC, dcode, odt, fused):
+    """FMM_DC_BF16 when the upstream gradient is stored as bfloat16 (with bfloat16 A, B
+    and the fused adjoint only), else 0; raises for any other dC dtype."""
+    if dC.dtype == odt:
+        return 0
+    if dC.dtype == torch.bfloat16 and dcode == C.FMM_BF16:
+        if not fused:
+            raise ValueError("a bfloat16 dC needs the fused adjoint")
+        return C.FMM_DC_BF16
+    raise TypeError(f"dC must be {odt}" + (" or bfloat16" if dcode == C.FMM_BF16 else ""))
+
+
 def fusedmm_a_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fused=True, R_ws=None, dP_ws=None):
+    """Adjoint of FusedMMA for upstream gradient dC (m x r): dA by the row pass, dB by
+    the two-row column pass.  With bfloat16 A and B, dC may be bfloat16 as well (fused
+    only): the passes then read it as stored."""
     r = A.shape[1]
     dcode, odt = _common(P, A, B)
     _check_dense("dC", dC, P.m, r, P.device)
-    if dC.dtype != odt:
-        raise TypeError(f"dC must be {odt}")
+    dflag = _dc_flag(dC, dcode, odt, fused)
     if need[0] and dA is None:
         dA = torch.empty(P.m, r, dtype=odt, device=P.device)
     if need[1] and dB is None:
@@ -442,16 +456,17 @@ def fusedmm_a_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fus
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A_BWD, r, dcode)
     C.call("fmm_fusedmm_a_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
            dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
-           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
+           (C.FMM_FUSED if fused else C.FMM_UNFUSED) | dflag, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
     return dA, dB
 
 
 def fusedmm_b_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fused=True, R_ws=None, dP_ws=None):
+    """Adjoint of FusedMMB for upstream gradient dC (n x r); dC may be bfloat16 as for
+    fusedmm_a_backward_raw."""
     r = A.shape[1]
     dcode, odt = _common(P, A, B)
     _check_dense("dC", dC, P.n, r, P.device)
-    if dC.dtype != odt:
-        raise TypeError(f"dC must be {odt}")
+    dflag = _dc_flag(dC, dcode, odt, fused)
     if need[0] and dA is None:
         dA = torch.empty(P.m, r, dtype=odt, device=P.device)
     if need[1] and dB is None:
@@ -461,7 +476,7 @@ def fusedmm_b_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fus
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B_BWD, r, dcode)
     C.call("fmm_fusedmm_b_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
            dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
-           C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
+           (C.FMM_FUSED if fused else C.FMM_UNFUSED) | dflag, _ptr(R_ws), _ptr(dP_ws), _ptr(ws), wb, _stream())
     return dA, dB
 
 

@@ -105,6 +105,13 @@ def test_argument_errors_backward_and_prep():
     assert lib.fmm_fusedmm_b_backward(None, ctypes.byref(csc), *args) == -1
     uargs = (FAKE, FAKE, FAKE, 32, C.FMM_F32, FAKE, FAKE, C.FMM_UNFUSED, None, None, None, 0, None)
     assert lib.fmm_fusedmm_a_backward(ctypes.byref(csr), ctypes.byref(csc), *uargs) == -7
+    # a bfloat16 dC: bfloat16 storage and the fused adjoint only; other flag bits are errors
+    for fn in (lib.fmm_fusedmm_a_backward, lib.fmm_fusedmm_b_backward):
+        for dtype, flags, want in ((C.FMM_F32, C.FMM_DC_BF16, -8), (C.FMM_F64, C.FMM_DC_BF16, -8),
+                                   (C.FMM_BF16, C.FMM_UNFUSED | C.FMM_DC_BF16, -8), (C.FMM_BF16, 4, -2),
+                                   (C.FMM_F32, 4, -2)):
+            fargs = (FAKE, FAKE, FAKE, 32, dtype, FAKE, FAKE, flags, None, None, None, 0, None)
+            assert fn(ctypes.byref(csr), ctypes.byref(csc), *fargs) == want, (dtype, flags)
     nb = ctypes.c_size_t(0)
     assert lib.fmm_csr_to_csc_workspace(10, 10, 100, ctypes.byref(nb)) == 0 and nb.value > 800
     assert lib.fmm_csr_to_csc_workspace(-1, 10, 100, ctypes.byref(nb)) == -2
