@@ -547,11 +547,20 @@ def spmm_b_raw(P, A, w=None, w_order=C.FMM_CSR, out=None, beta=0.0):
 
 # ---------------------------------------------------------------- autograd functions
 
+def _upstream(dC, A, grad_bf16):
+    """The upstream gradient as the adjoint reads it: rounded to bfloat16 storage when
+    asked for (bfloat16 A and B only), else as given."""
+    dC = dC.contiguous()
+    if grad_bf16 and A.dtype == torch.bfloat16 and dC.dtype == torch.float32:
+        return to_bf16(dC)
+    return dC
+
+
 class _FusedMMA(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, P, A, B, fused):
+    def forward(ctx, P, A, B, fused, grad_bf16):
         C_out, R_ws = fusedmm_a_raw(P, A, B, fused=fused)
-        ctx.P, ctx.fused, ctx.R = P, fused, R_ws
+        ctx.P, ctx.fused, ctx.R, ctx.grad_bf16 = P, fused, R_ws, grad_bf16
         ctx.save_for_backward(A, B)
         return C_out
 
@@ -560,16 +569,17 @@ class _FusedMMA(torch.autograd.Function):
         A, B = ctx.saved_tensors
         need = (ctx.needs_input_grad[1], ctx.needs_input_grad[2])
         if not any(need):
-            return None, None, None, None
-        dA, dB = fusedmm_a_backward_raw(ctx.P, A, B, dC.contiguous(), need=need, fused=ctx.fused, R_ws=ctx.R)
-        return None, dA, dB, None
+            return None, None, None, None, None
+        dA, dB = fusedmm_a_backward_raw(ctx.P, A, B, _upstream(dC, A, ctx.grad_bf16), need=need, fused=ctx.fused,
+                                        R_ws=ctx.R)
+        return None, dA, dB, None, None
 
 
 class _FusedMMB(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, P, A, B, fused):
+    def forward(ctx, P, A, B, fused, grad_bf16):
         C_out, R_ws = fusedmm_b_raw(P, A, B, fused=fused)
-        ctx.P, ctx.fused, ctx.R = P, fused, R_ws
+        ctx.P, ctx.fused, ctx.R, ctx.grad_bf16 = P, fused, R_ws, grad_bf16
         ctx.save_for_backward(A, B)
         return C_out
 
@@ -578,9 +588,10 @@ class _FusedMMB(torch.autograd.Function):
         A, B = ctx.saved_tensors
         need = (ctx.needs_input_grad[1], ctx.needs_input_grad[2])
         if not any(need):
-            return None, None, None, None
-        dA, dB = fusedmm_b_backward_raw(ctx.P, A, B, dC.contiguous(), need=need, fused=ctx.fused, R_ws=ctx.R)
-        return None, dA, dB, None
+            return None, None, None, None, None
+        dA, dB = fusedmm_b_backward_raw(ctx.P, A, B, _upstream(dC, A, ctx.grad_bf16), need=need, fused=ctx.fused,
+                                        R_ws=ctx.R)
+        return None, dA, dB, None, None
 
 
 class _FusedMMValues(torch.autograd.Function):
@@ -687,20 +698,24 @@ class _SpMMB(torch.autograd.Function):
         return None, dA, (dw[:P.nnz] if dw is not None else None)
 
 
-def fusedmm_a(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None):
+def fusedmm_a(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None,
+              grad_bf16: bool = False):
     """FusedMMA(S, A, B) = SpMMA(SDDMM(A, B, S), B), differentiable in A and B, and in
-    S's stored values when they are given as ``values`` (nnz, CSR order)."""
+    S's stored values when they are given as ``values`` (nnz, CSR order).  grad_bf16
+    (bfloat16 A and B, fused): the adjoint reads the upstream gradient rounded to
+    bfloat16, which halves the bytes its column pass gathers for it."""
     if values is not None:
         return _FusedMMValues.apply(P, A, B, values, "a", fused)
-    return _FusedMMA.apply(P, A, B, fused)
+    return _FusedMMA.apply(P, A, B, fused, grad_bf16)
 
 
-def fusedmm_b(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None):
+def fusedmm_b(P: Pattern, A, B, fused: bool = True, values: Optional[torch.Tensor] = None,
+              grad_bf16: bool = False):
     """FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A), differentiable in A and B, and in
-    S's stored values when they are given as ``values``."""
+    S's stored values when they are given as ``values``; grad_bf16 as for fusedmm_a."""
     if values is not None:
         return _FusedMMValues.apply(P, A, B, values, "b", fused)
-    return _FusedMMB.apply(P, A, B, fused)
+    return _FusedMMB.apply(P, A, B, fused, grad_bf16)
 
 
 def sddmm(P: Pattern, A, B):

@@ -68,3 +68,23 @@ def test_bf16_upstream_gradient_errors():
         F.fusedmm_a_backward_raw(P, F.to_bf16(A), F.to_bf16(B), F.to_bf16(G), fused=False)
     with pytest.raises(TypeError):
         F.fusedmm_b_backward_raw(P, F.to_bf16(A), F.to_bf16(B), dev(dense_normal(40, 16, 4), torch.float64))
+
+
+def test_bf16_upstream_gradient_autograd():
+    """fusedmm_a/b(..., grad_bf16=True): the backward hands the fused adjoint the upstream
+    gradient rounded to bfloat16 (the engine then casts the float32 gradients to the
+    bfloat16 leaves' dtype)."""
+    S = rmat(10, 8, seed=630)
+    r = 64
+    P = F.Pattern.from_csr(S, long_len=64, chunk=32)
+    A16, B16 = F.to_bf16(dev(dense_normal(S.m, r, 631))), F.to_bf16(dev(dense_normal(S.n, r, 632)))
+    for form, fn, raw, rows in (("a", F.fusedmm_a, F.fusedmm_a_backward_raw, S.m),
+                                ("b", F.fusedmm_b, F.fusedmm_b_backward_raw, S.n)):
+        log(f"dC bf16 autograd form={form}")
+        G = dev(dense_normal(rows, r, 633))
+        for grad_bf16 in (True, False):
+            At, Bt = A16.clone().requires_grad_(True), B16.clone().requires_grad_(True)
+            (fn(P, At, Bt, grad_bf16=grad_bf16) * G).sum().backward()
+            eA, eB = raw(P, A16, B16, F.to_bf16(G) if grad_bf16 else G)
+            assert At.grad.dtype == torch.bfloat16
+            assert torch.equal(At.grad, eA.to(torch.bfloat16)) and torch.equal(Bt.grad, eB.to(torch.bfloat16))
