@@ -199,6 +199,7 @@ def pmc_summary(fetch_dir, write_dir, out_json, command="", workload_name=None, 
     print(json.dumps(out, indent=1))
 
 
+ROUNDING = "bf16 rounding (A, B once; dC every step with a bf16 upstream gradient)"
 ROLES = {0: "SDDMM", 1: "SpMM, one operand", 2: "SpMM, two operands (dB = dP^T A + R^T dC)",
          3: "fused one-row (FusedMMA forward / adjoint row pass)", 4: "fused two-row (adjoint column pass)"}
 
@@ -211,7 +212,7 @@ def _role(key):
     if "batch_kernel<" in key:
         return "batched persistent (all passes of every graph)"
     if "f32_to_bf16" in key:
-        return "bf16 rounding of A, B"
+        return ROUNDING
     return None
 
 
@@ -267,7 +268,9 @@ def counter_table(out_md, runs, command=""):
             gbs = b / avg_ns
             lines.append(f"| `{k}` | {role} | {calls} | {avg_ns / 1e3:.1f} | {b / 1e6:.1f} | {gbs:.0f} | "
                          f"{100 * gbs / HBM_PEAK_GBS:.1f} |")
-            if role != "bf16 rounding of A, B":
+            # the rounding of A and B happens once, before the steps; with a bf16 upstream
+            # gradient the rounding of dC is part of every step (and A, B share the kernel)
+            if role != ROUNDING or "dc_bf16" in name:
                 tot_b += b * calls
                 tot_t += avg_ns * calls
         if tot_t > 0:
@@ -656,7 +659,7 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
         dP_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
         step = make_step(A, B, fused=False, R_ws=R_ws, dP_ws=dP_ws)
     else:
-        step = make_step(F.to_bf16(A), F.to_bf16(B), fused=True)
+        step = make_step(F.to_bf16(A), F.to_bf16(B), fused=True, dc_bf16=args.profile_step == "fused_bf16_dc_bf16")
     t, kt = time_steps(step, args.steps, args.warmup)
     if args.calibrate_copy:
         calibrate_copy(dev)
@@ -682,7 +685,7 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--counter-table", nargs="+", metavar="OUT_MD NAME=TRACE:FETCH:WRITE",
                     help="markdown table of counter-measured traffic per hot-path kernel and step variant")
-    ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16"),
+    ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16", "fused_bf16_dc_bf16"),
                     help="run only this step variant, for profiling (no autotune: the batch depth and split "
                          "threshold come from --tuned, else the defaults)")
     ap.add_argument("--tuned", default="",
@@ -745,17 +748,20 @@ def main():
 
     kinds = ("fwd", "bwd_row", "bwd_col")
 
-    def make_step(Ai, Bi, fused=True, R_ws=None, dP_ws=None):
+    def make_step(Ai, Bi, fused=True, R_ws=None, dP_ws=None, dc_bf16=False):
+        # dc_bf16: the upstream gradient is rounded to bfloat16 in the step (timed with the
+        # row pass) and both adjoint passes read it as stored
         def step(ev=None):
             if ev is not None:
                 ev[0].record()
             F.fusedmm_a_raw(P, Ai, Bi, out=C, fused=fused, R_ws=R_ws)
             if ev is not None:
                 ev[1].record()
-            F.fusedmm_a_backward_raw(P, Ai, Bi, G, dA=dA, need=(True, False), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
+            Gs = F.to_bf16(G) if dc_bf16 else G
+            F.fusedmm_a_backward_raw(P, Ai, Bi, Gs, dA=dA, need=(True, False), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
             if ev is not None:
                 ev[2].record()
-            F.fusedmm_a_backward_raw(P, Ai, Bi, G, dB=dB, need=(False, True), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
+            F.fusedmm_a_backward_raw(P, Ai, Bi, Gs, dB=dB, need=(False, True), fused=fused, R_ws=R_ws, dP_ws=dP_ws)
             if ev is not None:
                 ev[3].record()
         return step
@@ -844,22 +850,8 @@ def main():
                                   "tuning_arg": tuning_arg(P.tuning)}
         log(f"fused bf16 step {t_bf * 1e3:.3f} ms")
 
-        # bfloat16 upstream gradient as well: the step rounds G to bfloat16 (inside the
-        # timed step) and both adjoint passes read it as stored
-        def step_dc16(ev=None):
-            if ev is not None:
-                ev[0].record()
-            F.fusedmm_a_raw(P, A16, B16, out=C)
-            if ev is not None:
-                ev[1].record()
-            G16 = F.to_bf16(G)
-            F.fusedmm_a_backward_raw(P, A16, B16, G16, dA=dA, need=(True, False))
-            if ev is not None:
-                ev[2].record()
-            F.fusedmm_a_backward_raw(P, A16, B16, G16, dB=dB, need=(False, True))
-            if ev is not None:
-                ev[3].record()
-        t_bg, kt_bg = time_steps(step_dc16, vsteps, 2)
+        # bfloat16 upstream gradient as well (rounded inside the timed step)
+        t_bg, kt_bg = time_steps(make_step(A16, B16, fused=True, dc_bf16=True), vsteps, 2)
         variants["fused_bf16_dc_bf16"] = {"ms_per_step": round(t_bg * 1e3, 4), "gflops": round(flops / t_bg / 1e9, 1),
                                           "kernel_ms": {k: round(v, 4) for k, v in kt_bg.items()},
                                           "note": "dC rounded to bfloat16 in the step (in the bwd_row time)"}
