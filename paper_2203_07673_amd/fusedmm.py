@@ -296,6 +296,11 @@ class Pattern:
         r = A.shape[1]
         dcode, odt = _common(self, A, B)
         rows_out = self.m if form == "a" else self.n
+        # the library's autotuner reads dC as float32 (float64 on the F64 path); a bfloat16
+        # upstream gradient is tuned with its float32 original
+        _check_dense("dC", dC, rows_out, r, self.device)
+        if dC.dtype != odt:
+            raise TypeError(f"autotune takes dC as {odt}")
         C_out = torch.empty(rows_out, r, dtype=odt, device=self.device)
         dA = torch.empty(self.m, r, dtype=odt, device=self.device)
         dB = torch.empty(self.n, r, dtype=odt, device=self.device)

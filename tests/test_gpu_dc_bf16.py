@@ -68,6 +68,10 @@ def test_bf16_upstream_gradient_errors():
         F.fusedmm_a_backward_raw(P, F.to_bf16(A), F.to_bf16(B), F.to_bf16(G), fused=False)
     with pytest.raises(TypeError):
         F.fusedmm_b_backward_raw(P, F.to_bf16(A), F.to_bf16(B), dev(dense_normal(40, 16, 4), torch.float64))
+    with pytest.raises(TypeError):  # the autotuner reads dC as float32
+        P.autotune(F.to_bf16(A), F.to_bf16(B), F.to_bf16(G))
+    with pytest.raises(ValueError):  # and checks its shape before any launch
+        P.autotune(A, B, G[:10])
 
 
 def test_bf16_upstream_gradient_autograd():
