@@ -23,7 +23,6 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-NO_SPLIT = 1 << 30  # a split threshold no line reaches
 METRIC = "FusedMM fwd+bwd GFLOP/s and % HBM peak; fused/BF16 vs unfused FP32 at tol"
 
 
@@ -557,14 +556,8 @@ def run_als(args):
 
 
 def restore_tuning(P, tuning):
-    """Put back an autotuned configuration (P.tuning): per orientation the split
-    threshold, the line order and the batch depth."""
-    from paper_2203_07673_amd import _capi as CA
-    for o, k in ((CA.FMM_CSR, "csr"), (CA.FMM_CSC, "csc")):
-        t = tuning[k]
-        P.set_split(o, t["long_len"] if t["long_len"] is not None else NO_SPLIT)
-        P.set_line_order(o, t["line_order"])
-    P.set_variant(tuning["csr"]["variant"], tuning["csc"]["variant"])
+    """Put back an autotuned configuration (P.tuning)."""
+    P.apply_tuning(tuning)
 
 
 def tuning_arg(tuning):

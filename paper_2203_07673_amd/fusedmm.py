@@ -369,6 +369,17 @@ class Pattern:
         return {k: {"variant": (self.csr if k == "csr" else self.csc).variant, "long_len": sp[k],
                     "line_order": self.orders[k] is not None} for k in ("csr", "csc")}
 
+    def apply_tuning(self, tuning):
+        """Put back a configuration that `tuning` reported (for instance one saved as JSON
+        after `autotune` on the same pattern): per orientation the split threshold, the
+        line order and the batch depth.  Results are then those of the tuned pattern, bit
+        for bit."""
+        for orient, key in ((C.FMM_CSR, "csr"), (C.FMM_CSC, "csc")):
+            t = tuning[key]
+            self.set_split(orient, t["long_len"] if t["long_len"] is not None else _NO_SPLIT)
+            self.set_line_order(orient, bool(t["line_order"]))
+        self.set_variant(tuning["csr"]["variant"], tuning["csc"]["variant"])
+
     @property
     def splits(self):
         """Split threshold (long_len) of each orientation's schedule, None without one."""

@@ -75,3 +75,25 @@ def test_er1m_every_tuning_sampled():
 @pytest.mark.timeout(900)
 def test_rmat20_r64_every_tuning_sampled():
     _check_all("rmat20", workload("rmat20_ef16_r64"), (torch.float32, torch.bfloat16), k=512)
+
+
+def test_apply_tuning_restores_an_autotuned_configuration():
+    """A tuning saved as JSON and applied to a fresh pattern of the same matrix gives the
+    same configuration and the same results, bit for bit."""
+    import json
+
+    from workloads import dense_normal, rmat
+
+    S = rmat(12, 8, seed=700)
+    r = 64
+    A, B, G = dev(dense_normal(S.m, r, 701)), dev(dense_normal(S.n, r, 702)), dev(dense_normal(S.m, r, 703))
+    log("apply_tuning")
+    P = F.Pattern.from_csr(S)
+    P.autotune(A, B, G, form="a")
+    saved = json.loads(json.dumps(P.tuning))
+    Q = F.Pattern.from_csr(S)
+    Q.apply_tuning(saved)
+    assert Q.tuning == P.tuning
+    out = {name: (F.fusedmm_a_raw(X, A, B)[0],) + F.fusedmm_a_backward_raw(X, A, B, G)
+           for name, X in (("tuned", P), ("restored", Q))}
+    assert all(torch.equal(x, y) for x, y in zip(out["tuned"], out["restored"]))
