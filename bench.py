@@ -53,6 +53,39 @@ def kernel_bytes_min(kind, m, n, nnz, r, e):
     raise ValueError(kind)
 
 
+def gat_forward_bytes(n, nnz, r, e):
+    """Gather-model bytes of one attention head's forward: the scores pass reads H once and
+    writes s, t; the line pass reads rowptr, colidx + value and t_j per entry, gathers H_j
+    per entry and writes out and lse per row."""
+    return e * n * r + 8 * n + 4 * (n + 1) + nnz * (8 + 4 + e * r) + n * (4 * r + 4 + 4)
+
+
+def gat_backward_bytes(n, nnz, r, e):
+    """Gather-model bytes of one attention head's adjoint: the row pass (held dO_i and
+    out_i, per entry colidx + value, t_j and a gathered H_j, dS written) writes D_i and the
+    packed row scalars; the column pass (held H_j, per entry rowidx + value, the packed row
+    scalars and a gathered dO_i) writes dt_j and dH_j; the da pass reads H, ds and dt."""
+    rows = 4 * (n + 1) + n * (8 * r + 8) + nnz * (8 + 4 + e * r + 4) + n * (4 + 12)
+    cols = 4 * (n + 1) + n * (e * r + 4 * r + 4) + nnz * (8 + 12 + 4 * r)
+    da = n * (e * r + 8)
+    return rows + cols + da
+
+
+def als_sweep_bytes(m, n, nnz, r, cg_steps=10):
+    """Gather-model bytes of one ALS sweep (float32 factors): per side, the right-hand
+    side SpMM, the Gram pass of the start vector, the CG start (reads b, q, x; writes r, p)
+    and cg_steps fused CG passes, each holding p_i, gathering F_j per entry, reading X and
+    R and writing X, R, P and <R, R>."""
+    def side(lines):
+        index = 4 * (lines + 1) + 8 * nnz + 4 * r * nnz
+        rhs = index + 4 * lines * r
+        gram = index + 8 * lines * r
+        start = 20 * lines * r + 4 * lines
+        cg = index + 24 * lines * r + 8 * lines
+        return rhs + gram + start + cg_steps * cg
+    return side(m) + side(n)
+
+
 def cpu_baseline(w, target_s=15.0, single_s=6.0):
     """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload, with all
     of the host's threads (the reported value) and with one thread."""
@@ -497,17 +530,24 @@ def run_gat(args):
     tb32 = timeit(lambda: step_bwd(Hs), args.steps, args.warmup)
     fwd_lse(H16)
     tb16 = timeit(lambda: step_bwd(H16), args.steps, args.warmup)
-    # gather model per head: each stored entry fetches its feature row and t_j; rows read H once
-    # for the scores and write out once
     nnz, n = S.nnz, S.n
-    bytes32 = heads * (nnz * (4 * r + 12) + n * (4 * r + 4 * r + 12))
+    bytes32 = heads * gat_forward_bytes(n, nnz, r, 4)
+    bbytes32 = heads * gat_backward_bytes(n, nnz, r, 4)
+
+    def roofline(nbytes, t, what):
+        achieved = nbytes / t / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": what,
+                "bytes_per_step": int(nbytes), "bytes_model": "gather (each stored entry fetches its rows)"}
     out = {"metric": "graph-attention forward (4 heads, softmax) ms", "workload": "gat_rmat20_r128_h4",
            "nnz": nnz, "n": n, "r": r, "heads": heads,
            "fused_f32_ms": round(t32 * 1e3, 4), "fused_bf16_ms": round(t16 * 1e3, 4),
            "unfused_f32_ms": round(tu * 1e3, 4), "speedup_fused_f32_vs_unfused_f32": round(tu / t32, 3),
            "backward_f32_ms": round(tb32 * 1e3, 4), "backward_bf16_ms": round(tb16 * 1e3, 4),
            "train_step_f32_ms": round((t32 + tb32) * 1e3, 4),
-           "f32_gather_model_TBs": round(bytes32 / t32 / 1e12, 3), "tuning": tuning}
+           "roofline": roofline(bytes32, t32, "fused forward of every head, fp32 (scores, line pass, merges)"),
+           "roofline_backward": roofline(bbytes32, tb32, "adjoint of every head, fp32 (row, column, da passes)"),
+           "tuning": tuning}
     print(json.dumps(out), flush=True)
 
 
@@ -549,8 +589,14 @@ def run_als(args):
     loss = float(F.als_residual(P, A, B))
     # per sweep: 2 x 11 Gram passes (4 r nnz flops each) + 2 right-hand-side SpMMs (2 r nnz)
     flops = 2 * (11 * 4 * r * S.nnz + 2 * r * S.nnz)
+    nbytes = als_sweep_bytes(m, n, S.nnz, r)
+    achieved = nbytes / t / 1e9
     out = {"metric": "ALS sweep (20 batched CG iterations) ms", "workload": "als_er1m_d32_r128",
            "nnz": S.nnz, "r": r, "ms_per_sweep": round(t * 1e3, 3), "gflops": round(flops / t / 1e9, 1),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "whole sweep (right-hand sides, Gram passes, fused CG passes)",
+                        "bytes_per_sweep": int(nbytes), "bytes_model": "gather (each stored entry fetches F_j)"},
            "loss_start": loss0, "loss_after": loss, "sweeps_timed": sweeps}
     print(json.dumps(out), flush=True)
 

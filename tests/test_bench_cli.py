@@ -69,3 +69,17 @@ def test_counter_calibration_when_the_runs_number_dispatches_differently(tmp_pat
     _write_pmc(str(tmp_path / "w2"), "WRITE_SIZE", write[:6])
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w2"), out)
     assert json.load(open(out))["scale"] == {"FETCH_SIZE": None, "WRITE_SIZE": None}
+
+
+def test_application_byte_models():
+    n, nnz, r = 1 << 20, 16 << 20, 128
+    # bf16 features move fewer bytes than fp32 ones, by exactly the feature-row terms
+    f32, f16 = bench.gat_forward_bytes(n, nnz, r, 4), bench.gat_forward_bytes(n, nnz, r, 2)
+    assert f32 - f16 == 2 * r * (n + nnz)
+    assert bench.gat_backward_bytes(n, nnz, r, 4) > 2 * f32 - 8 * n * r  # two gathering passes
+    # one ALS side with no CG steps: rhs SpMM + Gram pass + CG start
+    one = bench.als_sweep_bytes(n, n, nnz, r, cg_steps=0) // 2
+    index = 4 * (n + 1) + 8 * nnz + 4 * r * nnz
+    assert one == 2 * index + 12 * n * r + 20 * n * r + 4 * n
+    per_cg = (bench.als_sweep_bytes(n, n, nnz, r, cg_steps=1) - 2 * one) // 2
+    assert per_cg == index + 24 * n * r + 8 * n
