@@ -530,6 +530,11 @@ def run_gat(args):
     tb32 = timeit(lambda: step_bwd(Hs), args.steps, args.warmup)
     fwd_lse(H16)
     tb16 = timeit(lambda: step_bwd(H16), args.steps, args.warmup)
+
+    def step_bwd_do16(Hl):  # bf16 features and a bf16 upstream gradient, rounded in the step
+        for h in range(heads):
+            F.gat_backward(P, Hl[h], a[h][0], a[h][1], outs[h], F.to_bf16(dOs[h]), softmax=True, lse=lses[h])
+    tb16g = timeit(lambda: step_bwd_do16(H16), args.steps, args.warmup)
     nnz, n = S.nnz, S.n
     bytes32 = heads * gat_forward_bytes(n, nnz, r, 4)
     bbytes32 = heads * gat_backward_bytes(n, nnz, r, 4)
@@ -544,6 +549,7 @@ def run_gat(args):
            "fused_f32_ms": round(t32 * 1e3, 4), "fused_bf16_ms": round(t16 * 1e3, 4),
            "unfused_f32_ms": round(tu * 1e3, 4), "speedup_fused_f32_vs_unfused_f32": round(tu / t32, 3),
            "backward_f32_ms": round(tb32 * 1e3, 4), "backward_bf16_ms": round(tb16 * 1e3, 4),
+           "backward_bf16_dO_bf16_ms": round(tb16g * 1e3, 4),
            "train_step_f32_ms": round((t32 + tb32) * 1e3, 4),
            "roofline": roofline(bytes32, t32, "fused forward of every head, fp32 (scores, line pass, merges)"),
            "roofline_backward": roofline(bbytes32, tb32, "adjoint of every head, fp32 (row, column, da passes)"),

@@ -460,8 +460,11 @@ fmm_status fmm_gat_edge_values(const fmm_sparse *S, const void *s, const void *t
  * Two passes over the pattern (rows on S_csr, columns on S_csc), each recomputing the
  * edge weights and dw in registers; no atomics, fixed summation orders.  Both
  * descriptors' split schedules and orders are honoured.  dtype as for fmm_gat_forward
- * (dO, out, dH, da1, da2, s, t, a1, a2 float32; float64 for FMM_F64).  ws: a device
- * workspace of fmm_gat_backward_workspace() bytes, 256-byte aligned.
+ * (dO, out, dH, da1, da2, s, t, a1, a2 float32; float64 for FMM_F64).  flags:
+ * FMM_GAT_SOFTMAX as in the forward, OR-ed with FMM_DC_BF16 (FMM_BF16 only, else
+ * FMM_ERR_UNSUPPORTED) when dO is stored as bfloat16: the row pass holds it and the
+ * column pass gathers it at 2 bytes per element; every output stays float32.  ws: a
+ * device workspace of fmm_gat_backward_workspace() bytes, 256-byte aligned.
  */
 fmm_status fmm_gat_backward_workspace(const fmm_sparse *S_csr, const fmm_sparse *S_csc, int32_t r, int32_t dtype,
                                       size_t *bytes);

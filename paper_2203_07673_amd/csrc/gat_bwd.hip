@@ -142,8 +142,8 @@ __device__ __forceinline__ void entry_grad(Acc v, Acc score, Acc lse_i, Acc D_i,
     dx = de * (x > Acc(0) ? Acc(1) : slope);
 }
 
-// (2) Row pass on S_csr: held dO_i, gathered H_j.  ds_i = sum_j dx_ij S_ij; dS_ij.
-template <class TH, class Acc, int L, int NV, int VW, int U>
+// (2) Row pass on S_csr: held dO_i (stored as TO), gathered H_j.  ds_i = sum_j dx_ij S_ij; dS_ij.
+template <class TH, class TO, class Acc, int L, int NV, int VW, int U>
 __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int32_t nb_chunk_blocks)
 {
     constexpr int GPB = kBlock / L;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
     int32_t line, begin, end, chunk;
     if (!pick_line(a, nb_chunk_blocks, GPB, threadIdx.x / L, line, begin, end, chunk)) return;
     const int r = a.r, C = r / VW;
-    const Acc *dO = static_cast<const Acc *>(a.held);
+    const TO *dO = static_cast<const TO *>(a.held);
     const TH *H = static_cast<const TH *>(a.gath);
     const Acc *val = static_cast<const Acc *>(a.val);
     const Acc *t = static_cast<const Acc *>(a.t);
@@ -170,7 +170,8 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
     for (int v = 0; v < NV; ++v) {
         act[v] = v * L + lane < C;
         off[v] = act[v] ? (v * L + lane) * VW : 0;
-        Raw<Acc, VW> x, y;
+        Raw<TO, VW> x;
+        Raw<Acc, VW> y;
         if (act[v]) {
             x.load(dO + (size_t)line * r + off[v]);
             y.load(out + (size_t)line * r + off[v]);
@@ -239,9 +240,9 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_rows_kernel(GatBwdArgs a, int3
     }
 }
 
-// (3) Column pass on the stored transpose: held H_j, gathered dO_i and the row scalars.
-// dt_j = sum_i dx_ij S_ij and sum_i w_ij dO_i.
-template <class TH, class Acc, int L, int NV, int VW, int U>
+// (3) Column pass on the stored transpose: held H_j, gathered dO_i (stored as TO) and the
+// row scalars.  dt_j = sum_i dx_ij S_ij and sum_i w_ij dO_i.
+template <class TH, class TO, class Acc, int L, int NV, int VW, int U>
 __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int32_t nb_chunk_blocks)
 {
     constexpr int GPB = kBlock / L;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
     if (!pick_line(a, nb_chunk_blocks, GPB, threadIdx.x / L, line, begin, end, chunk)) return;
     const int r = a.r, C = r / VW;
     const TH *H = static_cast<const TH *>(a.held);
-    const Acc *dO = static_cast<const Acc *>(a.gath);
+    const TO *dO = static_cast<const TO *>(a.gath);
     const Acc *val = static_cast<const Acc *>(a.val);
     const Acc tj = static_cast<const Acc *>(a.t)[line];
     const Acc slope = Acc(a.slope);
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void gat_bwd_cols_kernel(GatBwdArgs a, int3
         RowScalars<Acc> rsc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) ok[u] = p0 + u < end;
-        Raw<Acc, VW> g[U][NV];
+        Raw<TO, VW> g[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             rsc[u].load(a.rs, i[u]);
@@ -449,9 +450,9 @@ Shape bwd_shape(int r, int vw)
     return s;
 }
 
-template <class TH, class Acc, int L, int NV, int VW>
+template <class TH, class TO, class Acc, int L, int NV, int VW>
 hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const TH *H, const Acc *a1, const Acc *a2,
-                         const Acc *s, const Acc *t, const Acc *out, const Acc *lse, const Acc *dO, int32_t r,
+                         const Acc *s, const Acc *t, const Acc *out, const Acc *lse, const TO *dO, int32_t r,
                          Acc slope, bool softmax, Acc *dH, Acc *da1, Acc *da2, Acc *dS, char *ws, hipStream_t st)
 {
     constexpr int GPB = kBlock / L;
@@ -495,7 +496,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.part_sc = ws + lay.psc_r;
     a.dS = dS;
     int64_t nbc = a.n_chunks > 0 ? ((int64_t)a.n_chunks + GPB - 1) / GPB : 0;
-    hipLaunchKernelGGL((gat_bwd_rows_kernel<TH, Acc, L, NV, VW, UR>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
+    hipLaunchKernelGGL((gat_bwd_rows_kernel<TH, TO, Acc, L, NV, VW, UR>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
                        0, st, a, (int32_t)nbc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (S_csr->n_chunks > 0 && S_csr->n_splits > 0) {
@@ -525,7 +526,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
     a.part_sc = ws + lay.psc_c;
     a.dS = nullptr;
     nbc = a.n_chunks > 0 ? ((int64_t)a.n_chunks + GPB - 1) / GPB : 0;
-    hipLaunchKernelGGL((gat_bwd_cols_kernel<TH, Acc, L, NV, VW, UC>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
+    hipLaunchKernelGGL((gat_bwd_cols_kernel<TH, TO, Acc, L, NV, VW, UC>), dim3((unsigned)(nbc + nb_rows)), dim3(kBlock),
                        0, st, a, (int32_t)nbc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // (3) split columns: merge their chunks, then add their rank-one terms
@@ -555,7 +556,7 @@ hipError_t run_bwd_shape(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const
 
 #define BWD_SHAPES(X) X(1, 1) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(64, 2) X(64, 4)
 
-template <class TH, class Acc, int VW>
+template <class TH, class TO, class Acc, int VW>
 hipError_t dispatch_bwd(Shape sh, const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *H, const void *a1,
                         const void *a2, const void *s, const void *t, const void *out, const void *lse,
                         const void *dO, int32_t r,
@@ -564,9 +565,9 @@ hipError_t dispatch_bwd(Shape sh, const fmm_sparse *S_csr, const fmm_sparse *S_c
 {
 #define BWD_CASE(Lv, NVv)                                                                        \
     if (sh.L == Lv && sh.NV == NVv)                                                              \
-        return run_bwd_shape<TH, Acc, Lv, NVv, VW>(                                              \
+        return run_bwd_shape<TH, TO, Acc, Lv, NVv, VW>(                                          \
             S_csr, S_csc, (const TH *)H, (const Acc *)a1, (const Acc *)a2, (const Acc *)s, (const Acc *)t, \
-            (const Acc *)out, (const Acc *)lse, (const Acc *)dO, r, (Acc)slope, softmax, (Acc *)dH, (Acc *)da1, (Acc *)da2, \
+            (const Acc *)out, (const Acc *)lse, (const TO *)dO, r, (Acc)slope, softmax, (Acc *)dH, (Acc *)da1, (Acc *)da2, \
             (Acc *)dS, (char *)ws, st);
     BWD_SHAPES(BWD_CASE)
 #undef BWD_CASE
@@ -602,7 +603,9 @@ fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, co
     if (n < 0 || S_csr->cols != n || S_csc->rows != n || S_csc->cols != n || S_csr->nnz != S_csc->nnz ||
         S_csr->nnz < 0 || r < 1)
         return FMM_ERR_DIM;
-    if (flags & ~FMM_GAT_SOFTMAX) return FMM_ERR_DIM;
+    if (flags & ~(FMM_GAT_SOFTMAX | FMM_DC_BF16)) return FMM_ERR_DIM;
+    const bool do16 = (flags & FMM_DC_BF16) != 0;  // dO stored as bfloat16 (bfloat16 H only)
+    if (do16 && dtype != FMM_BF16) return FMM_ERR_UNSUPPORTED;
     if (!S_csr->ptr || !S_csc->ptr || (S_csr->nnz > 0 && (!S_csr->idx || !S_csc->idx))) return FMM_ERR_NULL;
     if (!a1 || !a2 || !da1 || !da2) return FMM_ERR_NULL;
     if (n > 0 && (!H || !s || !t || !out || !dO || !dH)) return FMM_ERR_NULL;
@@ -623,24 +626,26 @@ fmm_status fmm_gat_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, co
         if (vw == 4 && (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)))
             return FMM_ERR_UNSUPPORTED;
         const Shape sh = bwd_shape(r, vw);
-        e = vw == 4 ? dispatch_bwd<float, float, 4>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
+        e = vw == 4 ? dispatch_bwd<float, float, float, 4>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                     softmax, dH, da1, da2, dS, ws, stream)
-                    : dispatch_bwd<float, float, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
+                    : dispatch_bwd<float, float, float, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                     softmax, dH, da1, da2, dS, ws, stream);
     } else if (dtype == FMM_BF16) {
         if (r % 8 != 0 || r > 1024) return FMM_ERR_DTYPE;
         if (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)) return FMM_ERR_UNSUPPORTED;
-        e = dispatch_bwd<bf16_t, float, 8>(bwd_shape(r, 8), S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r,
-                                           negative_slope, softmax, dH, da1, da2, dS, ws, stream);
+        e = do16 ? dispatch_bwd<bf16_t, bf16_t, float, 8>(bwd_shape(r, 8), S_csr, S_csc, H, a1, a2, s, t, out, lse,
+                                                          dO, r, negative_slope, softmax, dH, da1, da2, dS, ws, stream)
+                 : dispatch_bwd<bf16_t, float, float, 8>(bwd_shape(r, 8), S_csr, S_csc, H, a1, a2, s, t, out, lse,
+                                                         dO, r, negative_slope, softmax, dH, da1, da2, dS, ws, stream);
     } else if (dtype == FMM_F64) {
         const int vw = r % 2 == 0 ? 2 : 1;
         if (r > 64 * 4 * vw) return FMM_ERR_DTYPE;
         if (vw == 2 && (misaligned(H) || misaligned(out) || misaligned(dO) || misaligned(dH)))
             return FMM_ERR_UNSUPPORTED;
         const Shape sh = bwd_shape(r, vw);
-        e = vw == 2 ? dispatch_bwd<double, double, 2>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
+        e = vw == 2 ? dispatch_bwd<double, double, double, 2>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                       softmax, dH, da1, da2, dS, ws, stream)
-                    : dispatch_bwd<double, double, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
+                    : dispatch_bwd<double, double, double, 1>(sh, S_csr, S_csc, H, a1, a2, s, t, out, lse, dO, r, negative_slope,
                                                       softmax, dH, da1, da2, dS, ws, stream);
     } else {
         return FMM_ERR_DTYPE;

@@ -793,13 +793,23 @@ def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=Tru
     """Adjoint of gat_forward: (dH, da1, da2, dS) for upstream gradient dO, from the
     forward's output ``out`` and, with the softmax, its ``lse`` (recomputed by a forward
     call when not given).  dS, the gradient for S's stored values in CSR order, only
-    with want_dS."""
+    with want_dS.  With bfloat16 H, dO may be bfloat16 as well (read as stored)."""
     r = H.shape[1]
     _check_dense("H", H, P.n, r, P.device)
     dcode, odt = _common(P, H, None)
     _check_dense("out", out, P.m, r, P.device)
+    if out.dtype != odt:
+        raise TypeError(f"out must be {odt}")
     dO = dO.contiguous()
     _check_dense("dO", dO, P.m, r, P.device)
+    if dO.dtype == odt:
+        dflag = 0
+    elif dO.dtype == torch.bfloat16 and dcode == C.FMM_BF16:
+        dflag = C.FMM_DC_BF16
+    else:
+        raise TypeError(f"dO must be {odt}" + (" or bfloat16" if dcode == C.FMM_BF16 else ""))
+    if lse is not None and (lse.dtype != odt or lse.numel() != P.m or not lse.is_contiguous()):
+        raise ValueError(f"lse must be a contiguous {odt} vector of {P.m} values")
     if softmax and lse is None:
         lse = torch.empty(P.m, dtype=odt, device=P.device)
         gat_forward(P, H, a1, a2, negative_slope, True, out=torch.empty_like(out), lse=lse)
@@ -817,8 +827,8 @@ def gat_backward(P: Pattern, H, a1, a2, out, dO, negative_slope=0.2, softmax=Tru
     C.call("fmm_gat_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(H), _ptr(a1.contiguous()),
            _ptr(a2.contiguous()), _ptr(s), _ptr(t), _ptr(out), _ptr(lse if softmax else None), _ptr(dO), r, dcode,
            float(negative_slope),
-           C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(dH), _ptr(da1), _ptr(da2), _ptr(dS), _ptr(ws), nb.value,
-           _stream())
+           (C.FMM_GAT_SOFTMAX if softmax else 0) | dflag, _ptr(dH), _ptr(da1), _ptr(da2), _ptr(dS), _ptr(ws),
+           nb.value, _stream())
     return dH, da1, da2, (dS[:P.nnz] if want_dS else None)
 
 

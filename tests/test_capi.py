@@ -225,7 +225,9 @@ def test_gat_backward_argument_errors():
     assert call(S1=None) == -1
     assert call(S1=_desc(orient=C.FMM_CSC, rows=5, cols=5)) == -4
     assert call(S1=_desc(rows=5, cols=6)) == -2                 # attention needs a square pattern
-    assert call(flags=2) == -2
+    assert call(flags=4) == -2                                   # an unknown flag bit
+    assert call(flags=C.FMM_GAT_SOFTMAX | C.FMM_DC_BF16) == -8    # a bf16 dO needs bf16 features
+    assert call(flags=C.FMM_DC_BF16, dtype=2) == -8
     assert call(dH=None) == -1
     assert call(da1=None) == -1
     assert call(wsb=0) == -7

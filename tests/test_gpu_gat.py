@@ -198,6 +198,36 @@ def test_gat_backward_parity(case):
                 _gate_max(f"{case} {dtype} softmax={softmax} {name}", host(got), want, tol)
 
 
+@pytest.mark.parametrize("case", [c[0] for c in BWD_CASES if c[2] % 8 == 0])
+def test_gat_backward_bf16_upstream_gradient(case):
+    """bf16 features and a bf16 dO (FMM_DC_BF16): against the oracle on the rounded H and
+    dO at the float32 gate, so the only extra error is dO's rounding; repeatable bit for
+    bit."""
+    _, build, r, split = [c for c in BWD_CASES if c[0] == case][0]
+    S = build()
+    H = dense_normal(S.n, r, 610)
+    a1 = dense_normal(1, r, 611, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 612, sigma=r ** -0.5)[0]
+    dO = dense_normal(S.m, r, 613)
+    P = F.Pattern.from_csr(S, long_len=64 if split else 1 << 30, chunk=32 if split else 1 << 30, split=split)
+    Hd, dO16 = F.to_bf16(dev(H)), F.to_bf16(dev(dO))
+    Hq, dOq = oracle.bf16_round(H), oracle.bf16_round(dO)
+    a1d, a2d = dev(a1), dev(a2)
+    for softmax in (True, False):
+        log(f"gat backward bf16 dO {case} softmax={softmax}")
+        out = F.gat_forward(P, Hd, a1d, a2d, softmax=softmax)
+        got = F.gat_backward(P, Hd, a1d, a2d, out, dO16, softmax=softmax, want_dS=True)
+        ref = oracle.gat_backward(S, Hq, a1, a2, dOq, slope=0.2, softmax=softmax)
+        for name, g, want in zip(("dH", "da1", "da2", "dS"), got, ref):
+            _gate_max(f"{case} bf16 dO softmax={softmax} {name}", host(g), want, TOL_F32)
+        again = F.gat_backward(P, Hd, a1d, a2d, out, dO16, softmax=softmax, want_dS=True)
+        assert all(torch.equal(x, y) for x, y in zip(got, again))
+    with pytest.raises(TypeError):  # float32 features take a float32 dO only
+        F.gat_backward(P, dev(H), a1d, a2d, F.gat_forward(P, dev(H), a1d, a2d), dO16)
+    with pytest.raises(TypeError):
+        F.gat_backward(P, Hd, a1d, a2d, out.double(), dO16)
+
+
 @pytest.mark.parametrize("softmax", [True, False])
 def test_gat_autograd_and_gradcheck(softmax):
     S = rmat(9, 8, seed=620)
