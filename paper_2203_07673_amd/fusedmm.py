@@ -1047,6 +1047,8 @@ class BatchPlan:
             x.A, x.B = A[g].data_ptr(), B[g].data_ptr()
             if backward:
                 _check_dense("dC", dC[g], P.m, r, dev)
+                if dC[g].dtype != torch.float32:
+                    raise TypeError("dC must be float32")
                 x.dC, x.dA, x.dB = dC[g].data_ptr(), self.dA[g].data_ptr(), self.dB[g].data_ptr()
             if forward:
                 x.C = self.C[g].data_ptr()

@@ -116,6 +116,8 @@ def test_batch_graph_replay_matches_eager():
 
 def test_batch_forward_only_and_oracle_bf16_rounded():
     graphs, pats, A, B, G = _setup(torch.bfloat16, nbatch=5, seed=80)
+    with pytest.raises(TypeError):  # the batched adjoint reads dC as float32
+        F.BatchPlan(pats, A, B, [F.to_bf16(g) for g in G])
     plan = F.BatchPlan(pats, A, B, forward=True, backward=False)
     log("batch forward only")
     plan.run()
