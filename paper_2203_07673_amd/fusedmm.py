@@ -25,8 +25,8 @@ import torch
 from . import _capi as C
 
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
-           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values", "gat_forward_unfused", "gat_backward", "gat",
-           "gat_autotune", "cg_lines", "als_residual",
+           "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values",
+           "gat_forward_unfused", "gat_backward", "gat", "gat_autotune", "cg_lines", "als_residual",
            "als_sweep", "stream_copy", "stream_read"]
 
 DEFAULT_LONG_LEN = 128
@@ -72,6 +72,25 @@ def _check_dense(name, t, rows, r, device):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({rows}, {r if r is not None else 'r'})")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous (row-major)")
+
+
+def _check_buf(name, t, device, dtype, shape=None, min_numel=None):
+    """A caller-supplied output or workspace tensor: on the pattern's device, of the dtype
+    the kernel writes or reads, contiguous, and of the right shape (or at least min_numel
+    elements), so that no launch touches memory outside it."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, pattern on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {min_numel}")
+    return t
 
 
 class Pattern:
@@ -420,9 +439,12 @@ def fusedmm_a_raw(P, A, B, out=None, fused=True, R_ws=None):
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
     dcode, odt = _common(P, A, B)
-    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, (P.m, r))
     if not fused and R_ws is None:
         R_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    elif R_ws is not None:
+        _check_buf("R_ws", R_ws, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A, r, dcode)
     C.call("fmm_fusedmm_a", ctypes.byref(P.csr), _ptr(A), _ptr(B), r, dcode, _ptr(out),
            C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(ws), wb, _stream())
@@ -434,9 +456,12 @@ def fusedmm_b_raw(P, A, B, out=None, fused=True, R_ws=None):
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
     dcode, odt = _common(P, A, B)
-    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, (P.n, r))
     if not fused and R_ws is None:
         R_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    elif R_ws is not None:
+        _check_buf("R_ws", R_ws, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B, r, dcode)
     C.call("fmm_fusedmm_b", ctypes.byref(P.csc), _ptr(A), _ptr(B), r, dcode, _ptr(out),
            C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(R_ws), _ptr(ws), wb, _stream())
@@ -465,10 +490,17 @@ def fusedmm_a_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fus
     dflag = _dc_flag(dC, dcode, odt, fused)
     if need[0] and dA is None:
         dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    elif need[0]:
+        _check_buf("dA", dA, P.device, odt, (P.m, r))
     if need[1] and dB is None:
         dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    elif need[1]:
+        _check_buf("dB", dB, P.device, odt, (P.n, r))
     if not fused and dP_ws is None:
         dP_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    for name, buf in (("R_ws", R_ws), ("dP_ws", dP_ws)):
+        if buf is not None:
+            _check_buf(name, buf, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A_BWD, r, dcode)
     C.call("fmm_fusedmm_a_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
            dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
@@ -485,10 +517,17 @@ def fusedmm_b_backward_raw(P, A, B, dC, dA=None, dB=None, need=(True, True), fus
     dflag = _dc_flag(dC, dcode, odt, fused)
     if need[0] and dA is None:
         dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    elif need[0]:
+        _check_buf("dA", dA, P.device, odt, (P.m, r))
     if need[1] and dB is None:
         dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    elif need[1]:
+        _check_buf("dB", dB, P.device, odt, (P.n, r))
     if not fused and dP_ws is None:
         dP_ws = torch.empty(max(1, P.nnz), dtype=odt, device=P.device)
+    for name, buf in (("R_ws", R_ws), ("dP_ws", dP_ws)):
+        if buf is not None:
+            _check_buf(name, buf, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B_BWD, r, dcode)
     C.call("fmm_fusedmm_b_backward", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
            dcode, _ptr(dA if need[0] else None), _ptr(dB if need[1] else None),
@@ -503,9 +542,14 @@ def fusedmm_a_backward_values_raw(P, A, B, dC, dS=None, dA=None, want_dA=False, 
     r = A.shape[1]
     dcode, odt = _common(P, A, B)
     _check_dense("dC", dC, P.m, r, P.device)
-    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else dS
+    if dC.dtype != odt:
+        raise TypeError(f"dC must be {odt}")
+    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else \
+        _check_buf("dS", dS, P.device, odt, min_numel=P.nnz)
     if want_dA and dA is None:
         dA = torch.empty(P.m, r, dtype=odt, device=P.device)
+    elif want_dA:
+        _check_buf("dA", dA, P.device, odt, (P.m, r))
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_A_BWD_VALUES, r, dcode)
     C.call("fmm_fusedmm_a_backward_values", ctypes.byref(P.csr), _ptr(A), _ptr(B), _ptr(dC), r, dcode, _ptr(dS),
            _ptr(dA if want_dA else None), C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(ws), wb, _stream())
@@ -518,9 +562,14 @@ def fusedmm_b_backward_values_raw(P, A, B, dC, dS=None, dB=None, want_dB=False, 
     r = A.shape[1]
     dcode, odt = _common(P, A, B)
     _check_dense("dC", dC, P.n, r, P.device)
-    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else dS
+    if dC.dtype != odt:
+        raise TypeError(f"dC must be {odt}")
+    dS = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if dS is None else \
+        _check_buf("dS", dS, P.device, odt, min_numel=P.nnz)
     if want_dB and dB is None:
         dB = torch.empty(P.n, r, dtype=odt, device=P.device)
+    elif want_dB:
+        _check_buf("dB", dB, P.device, odt, (P.n, r))
     ws, wb = P.workspace(C.FMM_OP_FUSEDMM_B_BWD_VALUES, r, dcode)
     C.call("fmm_fusedmm_b_backward_values", ctypes.byref(P.csr), ctypes.byref(P.csc), _ptr(A), _ptr(B), _ptr(dC), r,
            dcode, _ptr(dS), _ptr(dB if want_dB else None), C.FMM_FUSED if fused else C.FMM_UNFUSED, _ptr(ws), wb,
@@ -533,7 +582,8 @@ def sddmm_raw(P, A, B, out=None, orient=C.FMM_CSR, beta=0.0):
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
     dcode, odt = _common(P, A, B)
-    out = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(max(1, P.nnz), dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, min_numel=P.nnz)
     desc = P.csr if orient == C.FMM_CSR else P.csc
     C.call("fmm_sddmm", ctypes.byref(desc), _ptr(A), _ptr(B), r, dcode, _ptr(out), float(beta), None, 0, _stream())
     return out[:P.nnz]
@@ -543,7 +593,10 @@ def spmm_a_raw(P, B, w=None, out=None, beta=0.0):
     r = B.shape[1]
     _check_dense("B", B, P.n, r, P.device)
     dcode, odt = _common(P, B, None)
-    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, (P.m, r))
+    if w is not None:
+        _check_buf("w", w, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_SPMM_A, r, dcode)
     C.call("fmm_spmm_a", ctypes.byref(P.csr), _ptr(w), _ptr(B), r, dcode, _ptr(out), float(beta), _ptr(ws), wb,
            _stream())
@@ -554,7 +607,10 @@ def spmm_b_raw(P, A, w=None, w_order=C.FMM_CSR, out=None, beta=0.0):
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
     dcode, odt = _common(P, A, None)
-    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(P.n, r, dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, (P.n, r))
+    if w is not None:
+        _check_buf("w", w, P.device, odt, min_numel=P.nnz)
     ws, wb = P.workspace(C.FMM_OP_SPMM_B, r, dcode)
     C.call("fmm_spmm_b", ctypes.byref(P.csc), _ptr(w), w_order, _ptr(A), r, dcode, _ptr(out), float(beta),
            _ptr(ws), wb, _stream())
@@ -773,7 +829,8 @@ def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=Non
     _check_dense("H", H, P.n, r, P.device)
     dcode, odt = _common(P, H, None)
     s, t = gat_scores(H, a1, a2)
-    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else out
+    out = torch.empty(P.m, r, dtype=odt, device=P.device) if out is None else \
+        _check_buf("out", out, P.device, odt, (P.m, r))
     nb = ctypes.c_size_t(0)
     C.call("fmm_gat_workspace", ctypes.byref(P.csr), r, dcode, ctypes.byref(nb))
     ws = None

@@ -245,3 +245,21 @@ def test_stream_probe_argument_errors():
     assert lib.fmm_stream_read(FAKE, 64, 0, None, None) == -1
     assert lib.fmm_stream_read(FAKE, 24, 0, FAKE, None) == -2
     assert lib.fmm_stream_read(FAKE + 8, 64, 0, FAKE, None) == -8
+
+
+def test_caller_buffers_are_checked():
+    """Outputs and workspaces a caller hands in are checked for device, dtype, layout and
+    size before any launch (the kernels would write outside a short or narrow buffer)."""
+    import torch
+
+    from paper_2203_07673_amd.fusedmm import _check_buf
+    cpu = torch.device("cpu")
+    ok = torch.zeros(4, 3)
+    assert _check_buf("out", ok, cpu, torch.float32, (4, 3)) is ok
+    assert _check_buf("R_ws", torch.zeros(10), cpu, torch.float32, min_numel=10) is not None
+    for bad, exc in ((torch.zeros(4, 3, dtype=torch.float64), TypeError), (torch.zeros(3, 3), ValueError),
+                     (torch.zeros(3, 4).t(), ValueError), ([0.0] * 12, TypeError)):
+        with pytest.raises(exc):
+            _check_buf("out", bad, cpu, torch.float32, (4, 3))
+    with pytest.raises(ValueError):
+        _check_buf("R_ws", torch.zeros(9), cpu, torch.float32, min_numel=10)

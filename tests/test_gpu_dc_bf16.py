@@ -92,3 +92,28 @@ def test_bf16_upstream_gradient_autograd():
             eA, eB = raw(P, A16, B16, F.to_bf16(G) if grad_bf16 else G)
             assert At.grad.dtype == torch.bfloat16
             assert torch.equal(At.grad, eA.to(torch.bfloat16)) and torch.equal(Bt.grad, eB.to(torch.bfloat16))
+
+
+def test_raw_calls_check_caller_buffers():
+    """Caller-supplied outputs of the wrong shape, dtype or size are refused before any
+    launch."""
+    S = er_exact_degree(60, 50, 5, seed=640)
+    P = F.Pattern.from_csr(S)
+    A, B, G = dev(dense_normal(60, 16, 1)), dev(dense_normal(50, 16, 2)), dev(dense_normal(60, 16, 3))
+    log("caller buffers")
+    with pytest.raises(ValueError):
+        F.fusedmm_a_raw(P, A, B, out=torch.empty(59, 16, device="cuda"))
+    with pytest.raises(TypeError):
+        F.fusedmm_b_raw(P, A, B, out=torch.empty(50, 16, device="cuda", dtype=torch.float64))
+    with pytest.raises(ValueError):
+        F.fusedmm_a_raw(P, A, B, fused=False, R_ws=torch.empty(S.nnz - 1, device="cuda"))
+    with pytest.raises(ValueError):
+        F.fusedmm_a_backward_raw(P, A, B, G, dB=torch.empty(50, 8, device="cuda"))
+    with pytest.raises(ValueError):
+        F.sddmm_raw(P, A, B, out=torch.empty(S.nnz // 2, device="cuda"))
+    with pytest.raises(ValueError):
+        F.spmm_a_raw(P, B, w=torch.ones(3, device="cuda"))
+    with pytest.raises(TypeError):
+        F.fusedmm_a_backward_values_raw(P, A, B, G.double())
+    with pytest.raises(ValueError):
+        F.fusedmm_a_backward_values_raw(P, A, B, G, dS=torch.empty(2, device="cuda"))
