@@ -406,7 +406,7 @@ def run_batch(args):
     # counter-measured bytes per launch of the chosen schedule's kernel, when the committed
     # counter summary covers the current sources
     waves = 64 // info["lanes"]  # line groups sharing a wavefront in the wavefront-per-line schedule
-    kernel_key = (f"void fmm::batch_kernel<unsigned short, {info['lanes']}, 8, "
+    kernel_key = (f"void fmm::batch_kernel<unsigned short, float, {info['lanes']}, 8, "
                   f"{waves if info['row_schedule'] else 1}, {waves if info['col_schedule'] else 1}>")
     traffic = None
     f = os.path.join(ROOT, "profiles", "traffic_batch256_r64.json")
@@ -444,6 +444,25 @@ def run_batch(args):
         side.synchronize()
         t_eager = loop(lambda: plan.run(side))
         variants["eager_persistent_launch_ms"] = round(t_eager * 1e3, 3)
+        # the same batch with bfloat16 upstream gradients (already bfloat16 in HBM, as from a
+        # bfloat16 layer above): its own autotune and hipGraph
+        G16 = [F.to_bf16(g) for g in G]
+        plan16 = F.BatchPlan(pats, A, B, G16)
+        plan16.autotune()
+        plan16.capture(side)
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                plan16.launch(side)
+            side.synchronize()
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(side)
+            for _ in range(args.steps):
+                plan16.launch(side)
+            f1.record(side)
+            side.synchronize()
+        variants["batched_bf16_dc_bf16_ms"] = round(f0.elapsed_time(f1) / args.steps, 4)
+        variants["batched_bf16_dc_bf16_schedule"] = plan16.info()
+        del plan16, G16
 
     out = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,

@@ -531,13 +531,15 @@ fmm_status fmm_sddmm_residual(const fmm_sparse *S_csr, const void *A, const void
  */
 #define FMM_BATCH_FWD 1   /* compute C_g = FusedMMA(S_g, A_g, B_g)                        */
 #define FMM_BATCH_BWD 2   /* compute dA_g, dB_g for upstream gradient dC_g                */
+#define FMM_BATCH_DC_BF16 4 /* with FMM_BATCH_BWD and FMM_BF16: every dC_g is bfloat16     */
 
 typedef struct fmm_batch_graph {
     fmm_sparse csr;       /* rows x cols CSR descriptor of S_g (its split schedule is ignored) */
     fmm_sparse csc;       /* the stored transpose of S_g (required with FMM_BATCH_BWD)         */
     const void *A;        /* rows x r, storage dtype                                           */
     const void *B;        /* cols x r, storage dtype                                           */
-    const void *dC;       /* rows x r float32 upstream gradient (FMM_BATCH_BWD)                */
+    const void *dC;       /* rows x r upstream gradient (FMM_BATCH_BWD): float32, or bfloat16
+                             with FMM_BATCH_DC_BF16                                            */
     void *C;              /* rows x r float32 output (FMM_BATCH_FWD)                           */
     void *dA;             /* rows x r float32 output (FMM_BATCH_BWD)                           */
     void *dB;             /* cols x r float32 output (FMM_BATCH_BWD)                           */
@@ -561,7 +563,8 @@ typedef struct fmm_batch_info {
 /*
  * Build a plan for nbatch graphs with common r and dtype (FMM_F32 or FMM_BF16 storage;
  * r % (16 / element size) == 0 and r <= 64 * 16 / element size).  flags: FMM_BATCH_FWD
- * and/or FMM_BATCH_BWD.  Synchronous: copies the pointer arrays of every graph to the
+ * and/or FMM_BATCH_BWD, plus FMM_BATCH_DC_BF16 (FMM_BF16 with FMM_BATCH_BWD only, else
+ * FMM_ERR_UNSUPPORTED) when the upstream gradients are stored as bfloat16.  Synchronous: copies the pointer arrays of every graph to the
  * host to cut nnz-balanced tiles, then allocates and uploads the tables.  The default
  * schedule (before autotuning) is row-block, XCD-aware, tile_nnz 8192.  The graphs'
  * device buffers must stay valid for the life of the plan.

@@ -28,7 +28,7 @@ FMM_VARIANT_AUTO, FMM_VARIANT_DEEP, FMM_VARIANT_MEDIUM, FMM_VARIANT_SHALLOW = 0,
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_ERR_NULL", -2: "FMM_ERR_DIM", -3: "FMM_ERR_DTYPE", -4: "FMM_ERR_ORIENT",
                 -5: "FMM_ERR_INDEX", -6: "FMM_ERR_NONCANONICAL", -7: "FMM_ERR_WORKSPACE",
                 -8: "FMM_ERR_UNSUPPORTED", -9: "FMM_ERR_HIP", -10: "FMM_ERR_STATE"}
-FMM_BATCH_FWD, FMM_BATCH_BWD = 1, 2
+FMM_BATCH_FWD, FMM_BATCH_BWD, FMM_BATCH_DC_BF16 = 1, 2, 4
 FMM_GAT_SOFTMAX = 1
 
 

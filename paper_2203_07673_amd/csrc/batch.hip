@@ -52,8 +52,11 @@ fmm_status hipfail(hipError_t e)
 
 BatchKernelFn kernel_for(const fmm_batch_plan *p, int rw, int cw)
 {
-    if (p->dtype == FMM_BF16) return batch_kernel_for<bf16_t>(p->L, rw, cw);
-    return batch_kernel_for<float>(p->L, rw, cw);
+    if (p->dtype == FMM_BF16) {
+        if (p->flags & FMM_BATCH_DC_BF16) return batch_kernel_for<bf16_t, bf16_t>(p->L, rw, cw);
+        return batch_kernel_for<bf16_t, float>(p->L, rw, cw);
+    }
+    return batch_kernel_for<float, float>(p->L, rw, cw);
 }
 
 struct TileCost {
@@ -66,6 +69,7 @@ struct TileCost {
 void cut_tiles(const fmm_batch_plan *p, int32_t tile_nnz, std::vector<std::vector<TileCost>> *per_graph)
 {
     const double e = p->ebytes, r = p->r;
+    const double ed = (p->flags & FMM_BATCH_DC_BF16) ? 2 : 4;  // bytes per element of dC
     per_graph->assign(p->nbatch, {});
     for (int32_t g = 0; g < p->nbatch; ++g) {
         for (int pass = 0; pass < 3; ++pass) {
@@ -73,8 +77,8 @@ void cut_tiles(const fmm_batch_plan *p, int32_t tile_nnz, std::vector<std::vecto
             if (pass != PASS_FWD && !(p->flags & FMM_BATCH_BWD)) continue;
             const std::vector<int32_t> &ptr = pass == PASS_BWD_COL ? p->colptr[g] : p->rowptr[g];
             const int32_t nl = (int32_t)ptr.size() - 1;
-            const double per_entry = pass == PASS_BWD_COL ? (e + 4) * r + 8 : e * r + 8;
-            const double per_line = pass == PASS_FWD ? (e + 4) * r : pass == PASS_BWD_ROW ? 8 * r : (e + 4) * r;
+            const double per_entry = pass == PASS_BWD_COL ? (e + ed) * r + 8 : e * r + 8;
+            const double per_line = pass == PASS_FWD ? (e + 4) * r : pass == PASS_BWD_ROW ? (ed + 4) * r : (e + 4) * r;
             int32_t l0 = 0;
             while (l0 < nl) {
                 int32_t l1 = l0;
@@ -220,7 +224,9 @@ fmm_status fmm_batch_plan_create(const fmm_batch_graph *graphs, int32_t nbatch, 
     if (!graphs || !plan) return FMM_ERR_NULL;
     *plan = nullptr;
     if (nbatch < 1) return FMM_ERR_DIM;
-    if (flags <= 0 || (flags & ~(FMM_BATCH_FWD | FMM_BATCH_BWD))) return FMM_ERR_DIM;
+    if (!(flags & (FMM_BATCH_FWD | FMM_BATCH_BWD)) || (flags & ~(FMM_BATCH_FWD | FMM_BATCH_BWD | FMM_BATCH_DC_BF16)))
+        return FMM_ERR_DIM;
+    if ((flags & FMM_BATCH_DC_BF16) && (dtype != FMM_BF16 || !(flags & FMM_BATCH_BWD))) return FMM_ERR_UNSUPPORTED;
     int ebytes;
     if (dtype == FMM_F32) ebytes = 4;
     else if (dtype == FMM_BF16) ebytes = 2;
@@ -287,7 +293,7 @@ fmm_status fmm_batch_plan_create(const fmm_batch_graph *graphs, int32_t nbatch, 
             d.colptr = x.csc.ptr;
             d.rowidx = x.csc.idx;
             d.valT = static_cast<const float *>(x.csc.val);
-            d.dC = static_cast<const float *>(x.dC);
+            d.dC = x.dC;
             d.dA = static_cast<float *>(x.dA);
             d.dB = static_cast<float *>(x.dB);
             p->colptr[g].resize((size_t)x.csc.cols + 1);

@@ -15,7 +15,7 @@ struct BatchGraphDev {
     const int32_t *colptr, *rowidx;
     const float *valT;
     const void *A, *B;
-    const float *dC;
+    const void *dC;  // TD elements (float32, or bfloat16 with a bfloat16 upstream gradient)
     float *C, *dA, *dB;
     int32_t m, n;
 };
@@ -24,7 +24,8 @@ struct BatchTile {
     int32_t graph, pass, l0, l1;
 };
 
-template <class TS, int L, int VW, int GPL_R, int GPL_C>
+// TS: storage of A and B; TD: storage of dC.
+template <class TS, class TD, int L, int VW, int GPL_R, int GPL_C>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__restrict__ graphs,
                                                        const BatchTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ wg_off, int32_t r)
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__re
                         o, lane, gidx, line, b, e, g.C + (size_t)line * r, false);
                 } else {
                     o.H = g.dC;
-                    process_line<OP_FUSED1, float, TS, TS, float, L, 1, VW, UR, GPL_R, false>(
+                    process_line<OP_FUSED1, TD, TS, TS, float, L, 1, VW, UR, GPL_R, false>(
                         o, lane, gidx, line, b, e, g.dA + (size_t)line * r, false);
                 }
             }
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__re
             o.G2 = g.dC;
             for (int32_t line = tl.l0 + slot; line < tl.l1; line += LPB) {
                 const int32_t b = g.colptr[line], e = g.colptr[line + 1];
-                process_line<OP_FUSED2, TS, TS, float, float, L, 1, VW, UC, GPL_C, false>(
+                process_line<OP_FUSED2, TS, TS, TD, float, L, 1, VW, UC, GPL_C, false>(
                     o, lane, gidx, line, b, e, g.dB + (size_t)line * r, false);
             }
         }
@@ -84,6 +85,6 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchGraphDev *__re
 // Host-side launcher table for one storage type: (L, row schedule, column schedule).
 typedef void (*BatchKernelFn)(const BatchGraphDev *, const BatchTile *, const int32_t *, int32_t);
 
-template <class TS> BatchKernelFn batch_kernel_for(int L, int row_wave, int col_wave);
+template <class TS, class TD> BatchKernelFn batch_kernel_for(int L, int row_wave, int col_wave);
 
 }  // namespace fmm

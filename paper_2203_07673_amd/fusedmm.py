@@ -1072,7 +1072,8 @@ class BatchPlan:
     """Fused FusedMMA forward and/or adjoint over many graphs in one persistent launch.
 
     ``patterns[g]``, ``A[g]`` (rows x r), ``B[g]`` (cols x r) and, for the adjoint,
-    ``dC[g]`` (rows x r float32) describe graph g.  Outputs ``C``, ``dA``, ``dB`` are
+    ``dC[g]`` (rows x r float32; bfloat16 too when A and B are bfloat16, the same for
+    every graph) describe graph g.  Outputs ``C``, ``dA``, ``dB`` are
     allocated here (lists of float32 tensors).  ``autotune()`` picks the schedule,
     ``run()`` launches eagerly, ``capture(stream)`` records the launch in a hipGraph
     and ``launch(stream)`` replays it.
@@ -1089,6 +1090,11 @@ class BatchPlan:
         dcode = dtype_code(A[0])
         self.r, self.dcode = r, dcode
         flags = (C.FMM_BATCH_FWD if forward else 0) | (C.FMM_BATCH_BWD if backward else 0)
+        dc_dtype = dC[0].dtype if backward else torch.float32
+        if dc_dtype == torch.bfloat16 and dcode == C.FMM_BF16:
+            flags |= C.FMM_BATCH_DC_BF16
+        elif dc_dtype != torch.float32:
+            raise TypeError("dC must be float32" + (" or bfloat16" if dcode == C.FMM_BF16 else ""))
         self.C = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if forward else None
         self.dA = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
         self.dB = [torch.empty(P.n, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
@@ -1104,8 +1110,8 @@ class BatchPlan:
             x.A, x.B = A[g].data_ptr(), B[g].data_ptr()
             if backward:
                 _check_dense("dC", dC[g], P.m, r, dev)
-                if dC[g].dtype != torch.float32:
-                    raise TypeError("dC must be float32")
+                if dC[g].dtype != dc_dtype:
+                    raise TypeError("every graph's dC needs the same dtype")
                 x.dC, x.dA, x.dB = dC[g].data_ptr(), self.dA[g].data_ptr(), self.dB[g].data_ptr()
             if forward:
                 x.C = self.C[g].data_ptr()

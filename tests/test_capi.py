@@ -153,6 +153,11 @@ def test_batch_plan_argument_errors():
     assert create(arr, 2, 64, C.FMM_F64, 3, ctypes.byref(plan)) == -3
     assert create(arr, 2, 12, C.FMM_BF16, 3, ctypes.byref(plan)) == -3
     assert create(arr, 2, 2048, C.FMM_F32, 3, ctypes.byref(plan)) == -3
+    dc16 = C.FMM_BATCH_DC_BF16
+    assert create(arr, 2, 64, C.FMM_BF16, dc16, ctypes.byref(plan)) == -2        # no pass asked for
+    assert create(arr, 2, 64, C.FMM_BF16, 3 | 8, ctypes.byref(plan)) == -2       # an unknown flag bit
+    assert create(arr, 2, 64, C.FMM_F32, 3 | dc16, ctypes.byref(plan)) == -8     # bf16 dC needs bf16 storage
+    assert create(arr, 2, 64, C.FMM_BF16, 1 | dc16, ctypes.byref(plan)) == -8    # and the adjoint
     arr[1].csc = _desc(orient=C.FMM_CSR)
     assert create(arr, 2, 64, C.FMM_F32, 3, ctypes.byref(plan)) == -4
     arr[1].csc = _desc(orient=C.FMM_CSC, rows=9)

@@ -17,7 +17,7 @@ HIP_INCLUDE = "/opt/rocm/include"
 STRUCTS = {"fmm_sparse": C.fmm_sparse, "fmm_batch_graph": C.fmm_batch_graph, "fmm_batch_info": C.fmm_batch_info}
 CONSTANTS = ["FMM_ABI_VERSION", "FMM_OK", "FMM_F32", "FMM_BF16", "FMM_F64", "FMM_CSR", "FMM_CSC", "FMM_FUSED",
              "FMM_UNFUSED", "FMM_DC_BF16", "FMM_VARIANT_AUTO", "FMM_VARIANT_DEEP", "FMM_VARIANT_MEDIUM",
-             "FMM_VARIANT_SHALLOW", "FMM_BATCH_FWD", "FMM_BATCH_BWD", "FMM_GAT_SOFTMAX", "FMM_OP_SDDMM", "FMM_OP_SPMM_A", "FMM_OP_SPMM_B",
+             "FMM_VARIANT_SHALLOW", "FMM_BATCH_FWD", "FMM_BATCH_DC_BF16", "FMM_BATCH_BWD", "FMM_GAT_SOFTMAX", "FMM_OP_SDDMM", "FMM_OP_SPMM_A", "FMM_OP_SPMM_B",
              "FMM_OP_FUSEDMM_A", "FMM_OP_FUSEDMM_B", "FMM_OP_FUSEDMM_A_BWD", "FMM_OP_FUSEDMM_B_BWD",
              "FMM_OP_SDDMM_BWD", "FMM_OP_SPMM_A_BWD", "FMM_OP_SPMM_B_BWD", "FMM_OP_FUSEDMM_A_BWD_VALUES",
              "FMM_OP_FUSEDMM_B_BWD_VALUES"]

@@ -114,10 +114,40 @@ def test_batch_graph_replay_matches_eager():
         plan.launch(side)
 
 
+def test_batch_bf16_upstream_gradient():
+    """bf16 A, B and dC (FMM_BATCH_DC_BF16): every graph's adjoint within the float32 gate
+    of the oracle on the rounded A, B, dC, and within the bf16 gate of the oracle on the
+    float32 originals, under a row-block, a wavefront and the autotuned schedule."""
+    graphs, pats, A, B, G = _setup(torch.bfloat16, nbatch=8, seed=81)
+    G16 = [F.to_bf16(g) for g in G]
+    plan = F.BatchPlan(pats, A, B, G16)
+
+    def check(tag):
+        plan.run()
+        torch.cuda.synchronize()
+        for k, g in enumerate(graphs):
+            S = g["S"]
+            Aq, Bq, Gq = oracle.bf16_round(g["A"]), oracle.bf16_round(g["B"]), oracle.bf16_round(g["G"])
+            dA, dB, mA, mB = ref_fusedmm_a_backward(S, Aq, Bq, Gq)
+            gate(f"{tag} graph {k} dA", host(plan.dA[k]), dA, mA, TOL_F32)
+            gate(f"{tag} graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
+            dA, dB, mA, mB = ref_fusedmm_a_backward(S, g["A"], g["B"], g["G"])
+            gate(f"{tag} graph {k} dB vs float32 inputs", host(plan.dB[k]), dB, mB, TOL_BF16)
+    for rw, cw in ((False, False), (True, True)):
+        log(f"batch bf16 dC rw={rw} cw={cw}")
+        plan.set_schedule(tile_nnz=2048, xcd_aware=True, row_wave=rw, col_wave=cw)
+        check(f"bf16 dC rw={rw} cw={cw}")
+    log("batch bf16 dC autotune")
+    plan.autotune()
+    check("bf16 dC autotuned")
+
+
 def test_batch_forward_only_and_oracle_bf16_rounded():
     graphs, pats, A, B, G = _setup(torch.bfloat16, nbatch=5, seed=80)
-    with pytest.raises(TypeError):  # the batched adjoint reads dC as float32
-        F.BatchPlan(pats, A, B, [F.to_bf16(g) for g in G])
+    with pytest.raises(TypeError):  # one dC dtype for every graph
+        F.BatchPlan(pats, A, B, [F.to_bf16(g) for g in G[:-1]] + [G[-1]])
+    with pytest.raises(TypeError):  # float32 storage takes a float32 dC only
+        F.BatchPlan(pats, [a.float() for a in A], [b.float() for b in B], [F.to_bf16(g) for g in G])
     plan = F.BatchPlan(pats, A, B, forward=True, backward=False)
     log("batch forward only")
     plan.run()
