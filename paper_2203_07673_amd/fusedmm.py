@@ -936,11 +936,11 @@ def gat_autotune(P: Pattern, H, a1, a2, dO=None, negative_slope=0.2, softmax=Tru
 
 class _GAT(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, P, H, a1, a2, values, negative_slope, softmax):
+    def forward(ctx, P, H, a1, a2, values, negative_slope, softmax, grad_bf16):
         Q = P.with_values(values) if values is not None else P
         lse = torch.empty(P.m, dtype=_out_dtype(dtype_code(H)), device=P.device) if softmax else None
         out = gat_forward(Q, H, a1, a2, negative_slope=negative_slope, softmax=softmax, lse=lse)
-        ctx.Q, ctx.slope, ctx.softmax, ctx.lse = Q, negative_slope, softmax, lse
+        ctx.Q, ctx.slope, ctx.softmax, ctx.lse, ctx.grad_bf16 = Q, negative_slope, softmax, lse, grad_bf16
         ctx.save_for_backward(H, a1, a2, out)
         return out
 
@@ -948,15 +948,16 @@ class _GAT(torch.autograd.Function):
     def backward(ctx, dO):
         H, a1, a2, out = ctx.saved_tensors
         want_dS = ctx.needs_input_grad[4]
-        dH, da1, da2, dS = gat_backward(ctx.Q, H, a1, a2, out, dO, ctx.slope, ctx.softmax, want_dS=want_dS,
-                                        lse=ctx.lse)
-        return None, dH, da1, da2, dS, None, None
+        dH, da1, da2, dS = gat_backward(ctx.Q, H, a1, a2, out, _upstream(dO, H, ctx.grad_bf16), ctx.slope,
+                                        ctx.softmax, want_dS=want_dS, lse=ctx.lse)
+        return None, dH, da1, da2, dS, None, None, None
 
 
-def gat(P: Pattern, H, a1, a2, values=None, negative_slope=0.2, softmax=True):
+def gat(P: Pattern, H, a1, a2, values=None, negative_slope=0.2, softmax=True, grad_bf16: bool = False):
     """The attention head as a differentiable function of H, a1, a2 and, when given,
-    S's stored values (learned edge values, nnz in CSR order)."""
-    return _GAT.apply(P, H, a1, a2, values, negative_slope, softmax)
+    S's stored values (learned edge values, nnz in CSR order).  grad_bf16 (bfloat16 H):
+    the adjoint reads the upstream gradient rounded to bfloat16."""
+    return _GAT.apply(P, H, a1, a2, values, negative_slope, softmax, grad_bf16)
 
 
 def cg_lines(P: Pattern, orient, F, rhs, lam, iters, X):

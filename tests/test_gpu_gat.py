@@ -222,6 +222,12 @@ def test_gat_backward_bf16_upstream_gradient(case):
             _gate_max(f"{case} bf16 dO softmax={softmax} {name}", host(g), want, TOL_F32)
         again = F.gat_backward(P, Hd, a1d, a2d, out, dO16, softmax=softmax, want_dS=True)
         assert all(torch.equal(x, y) for x, y in zip(got, again))
+    # the autograd option hands the adjoint the rounded upstream gradient
+    Ht = Hd.clone().requires_grad_(True)
+    (F.gat(P, Ht, a1d, a2d, grad_bf16=True) * dev(dO)).sum().backward()
+    out = F.gat_forward(P, Hd, a1d, a2d)
+    eH = F.gat_backward(P, Hd, a1d, a2d, out, dO16)[0]
+    assert torch.equal(Ht.grad, eH.to(torch.bfloat16))
     with pytest.raises(TypeError):  # float32 features take a float32 dO only
         F.gat_backward(P, dev(H), a1d, a2d, F.gat_forward(P, dev(H), a1d, a2d), dO16)
     with pytest.raises(TypeError):
