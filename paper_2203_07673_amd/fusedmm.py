@@ -44,6 +44,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def dtype_code(t: torch.Tensor) -> int:
+    """The library dtype code of a dense operand (FMM_F32, FMM_BF16 or FMM_F64)."""
     if t.dtype == torch.float32:
         return C.FMM_F32
     if t.dtype == torch.bfloat16:
@@ -283,6 +284,7 @@ class Pattern:
         self._refresh(orient)
 
     def max_line(self, orient):
+        """Entries in the longest line of an orientation (rows for FMM_CSR, columns for FMM_CSC)."""
         ptr = self.rowptr if orient == C.FMM_CSR else self.colptr
         return int((ptr[1:] - ptr[:-1]).max().item()) if ptr.numel() > 1 else 0
 
@@ -303,6 +305,7 @@ class Pattern:
 
     @property
     def variants(self):
+        """Batch depth class of each orientation (FMM_VARIANT_*)."""
         return {"csr": self.csr.variant, "csc": self.csc.variant}
 
     def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES, orders=(False, True)):
@@ -406,6 +409,7 @@ class Pattern:
 
     @property
     def schedules(self):
+        """Split schedule of each orientation (a dict of its arrays and threshold), None without one."""
         return {"csr": self._csr_sched, "csc": self._csc_sched}
 
     def workspace(self, op: int, r: int, dcode: int):
@@ -435,6 +439,9 @@ def _common(P: Pattern, A, B):
 # ---------------------------------------------------------------- raw calls (no autograd)
 
 def fusedmm_a_raw(P, A, B, out=None, fused=True, R_ws=None):
+    """C = FusedMMA(S, A, B) = (S * (A B^T)) B (Section II; row form in Section IV-B), no autograd.
+    Fused: one pass with the sampled values in registers; unfused: SDDMM into R_ws, then
+    SpMM.  Returns (C, R_ws)."""
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
@@ -452,6 +459,8 @@ def fusedmm_a_raw(P, A, B, out=None, fused=True, R_ws=None):
 
 
 def fusedmm_b_raw(P, A, B, out=None, fused=True, R_ws=None):
+    """C' = FusedMMB(S, A, B) = (S * (A B^T))^T A, run as FusedMMA on the stored transpose with
+    A and B interchanged (Section IV-B), no autograd.  Returns (C', R_ws), R_ws in CSR order."""
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
@@ -578,6 +587,8 @@ def fusedmm_b_backward_values_raw(P, A, B, dC, dS=None, dB=None, want_dB=False, 
 
 
 def sddmm_raw(P, A, B, out=None, orient=C.FMM_CSR, beta=0.0):
+    """R = S * (A B^T) at the stored entries (Eq. (1)), in CSR order (or CSC order with
+    orient=FMM_CSC); out = beta out + R."""
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
     _check_dense("B", B, P.n, r, P.device)
@@ -590,6 +601,8 @@ def sddmm_raw(P, A, B, out=None, orient=C.FMM_CSR, beta=0.0):
 
 
 def spmm_a_raw(P, B, w=None, out=None, beta=0.0):
+    """SpMMA: out = beta out + W B, W the pattern with per-entry values w (CSR order; None =
+    S's values) (Section II)."""
     r = B.shape[1]
     _check_dense("B", B, P.n, r, P.device)
     dcode, odt = _common(P, B, None)
@@ -604,6 +617,8 @@ def spmm_a_raw(P, B, w=None, out=None, beta=0.0):
 
 
 def spmm_b_raw(P, A, w=None, w_order=C.FMM_CSR, out=None, beta=0.0):
+    """SpMMB: out = beta out + W^T A on the stored transpose; w in CSR order (read through
+    perm) or CSC order (w_order) (Section II)."""
     r = A.shape[1]
     _check_dense("A", A, P.m, r, P.device)
     dcode, odt = _common(P, A, None)
@@ -1063,6 +1078,7 @@ def set_tuning(lanes: int = 0, nv: int = 0):
 
 
 def device_info():
+    """Compute units and architecture name of the current device."""
     cu = ctypes.c_int32(0)
     buf = ctypes.create_string_buffer(64)
     C.call("fmm_device_info", ctypes.byref(cu), buf, 64)
@@ -1121,22 +1137,29 @@ class BatchPlan:
         C.call("fmm_batch_plan_create", arr, len(patterns), r, dcode, flags, ctypes.byref(self._plan))
 
     def autotune(self, stream=None):
+        """Time every candidate schedule and keep the fastest (synchronous); returns info()."""
         C.call("fmm_batch_autotune", self._plan, self._s(stream))
         return self.info()
 
     def set_schedule(self, tile_nnz=8192, xcd_aware=True, row_wave=False, col_wave=False):
+        """Choose the schedule by hand: tile size, XCD-aware placement, and the
+        wavefront-per-line schedule for the row passes and for the column pass."""
         C.call("fmm_batch_set_schedule", self._plan, tile_nnz, int(xcd_aware), int(row_wave), int(col_wave))
 
     def run(self, stream=None):
+        """One eager persistent launch of the current schedule."""
         C.call("fmm_batch_run", self._plan, self._s(stream))
 
     def capture(self, stream):
+        """Record the launch in a hipGraph on `stream` (a created, non-default stream)."""
         C.call("fmm_batch_capture", self._plan, self._s(stream))
 
     def launch(self, stream):
+        """Replay the captured hipGraph on `stream`."""
         C.call("fmm_batch_launch", self._plan, self._s(stream))
 
     def info(self):
+        """The current schedule, its tile count and the last autotune's record."""
         i = C.fmm_batch_info()
         C.call("fmm_batch_plan_info", self._plan, ctypes.byref(i))
         return {f: getattr(i, f) for f, _ in C.fmm_batch_info._fields_}
