@@ -165,6 +165,7 @@ FWD_SHAPES = [
     (lambda: rmat(10, 16, seed=117), 256, True),
     (lambda: er_exact_degree(130, 90, 20, seed=118), 96, False),
     (lambda: er_exact_degree(64, 64, 64, seed=119), 1024, False),
+    (lambda: er_exact_degree(80, 70, 12, seed=120), 512, False),   # the widest fp64 rows
 ]
 
 
@@ -222,7 +223,8 @@ def test_forward_parity(k):
         gate("SpMMB", host(F.spmm_b_raw(P, Ad)), refb, magb, tol)
 
 
-@pytest.mark.parametrize("k", [0, 3, 4, 6])
+# r = 1, 32, 64 (split), 256 (split), 96 (idle lanes), 1024 (widest fp32/bf16 rows), 512 (widest fp64)
+@pytest.mark.parametrize("k", [0, 3, 4, 6, 7, 8, 9])
 def test_backward_parity(k):
     build, r, split = FWD_SHAPES[k]
     S32 = build()
