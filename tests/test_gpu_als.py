@@ -52,6 +52,28 @@ def test_cg_lines_parity(dtype, iters, split):
         assert err <= 1e-4, (orient, err)
 
 
+@pytest.mark.parametrize("r", [128, 512])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_cg_lines_parity_wide_rows(dtype, r):
+    """The fused CG step (no split schedule) at the benchmark's r = 128 and at r = 512, where
+    a lane holds more than one 16-byte vector (fp32) or 64 lanes own a line (bf16)."""
+    S = rmat(10, 8, seed=530)
+    lam, iters = 1.0, 5
+    Fa = dense_normal(S.n, r, 531, sigma=r ** -0.5)
+    rhs = dense_normal(S.m, r, 532)
+    X0 = dense_normal(S.m, r, 533)
+    log(f"cg wide dtype={dtype} r={r}")
+    P = F.Pattern.from_csr(S, split=False)
+    assert P.schedules["csr"] is None
+    Fd = F.to_bf16(dev(Fa)) if dtype == torch.bfloat16 else dev(Fa)
+    Fq = oracle.bf16_round(Fa) if dtype == torch.bfloat16 else Fa
+    X = dev(X0).clone()
+    F.cg_lines(P, C.FMM_CSR, Fd, dev(rhs), lam, iters, X)
+    ref = oracle.cg_lines(S, Fq, rhs, lam, iters, X0)
+    err = _rowrel(host(X), ref)
+    assert err <= 1e-4, err
+
+
 def test_residual_and_als_sweeps_reduce_loss():
     m = n = 4096
     r = 16
