@@ -16,7 +16,10 @@
  * copy of S (Section IV-B).  The fused calls keep each sampled value R_ij in
  * registers between the two products instead of writing R to memory (the local
  * fused kernel the paper cites in Section IV-B).  Backward calls give the adjoints
- * with respect to A and B for a fixed S.
+ * with respect to A and B for a fixed S, and separate calls the gradient with
+ * respect to S's stored values.  Beyond these: the graph-attention head and its
+ * adjoint, batched CG for ALS (Section VI-E), batch plans over many graphs, and
+ * streaming probes for measurement.
  *
  * Conventions that hold for every call unless its comment says otherwise:
  *   * Pointers named in a call are DEVICE pointers; sizes and descriptors are host
@@ -24,7 +27,8 @@
  *     fmm_validate (a 4-byte flag) and the batch-plan calls (their own tables).
  *   * Dense matrices are row-major with r contiguous elements per row (row stride r).
  *     FMM_F32 and FMM_BF16 name the storage of A and B; S values, dC and every
- *     output are float32 for both.  FMM_F64 makes everything float64.
+ *     output are float32 for both (with FMM_BF16 the adjoints can also take dC as
+ *     bfloat16: FMM_DC_BF16).  FMM_F64 makes everything float64.
  *     Limits on r: FMM_F32 r <= 1024 when r % 4 == 0, else r <= 256; FMM_BF16
  *     r % 8 == 0 and r <= 1024; FMM_F64 r <= 512 when r is even, else r <= 256.
  *     When r*sizeof(elem) is a multiple of 16 the dense bases must be 16-byte
