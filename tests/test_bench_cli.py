@@ -83,3 +83,38 @@ def test_application_byte_models():
     assert one == 2 * index + 12 * n * r + 20 * n * r + 4 * n
     per_cg = (bench.als_sweep_bytes(n, n, nnz, r, cg_steps=1) - 2 * one) // 2
     assert per_cg == index + 24 * n * r + 8 * n
+
+
+def _write_stats(d, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "trace_kernel_stats.csv"), "w") as fh:
+        fh.write("Name,Calls,TotalDurationNs,AverageNs,Percentage,MinNs,MaxNs\n")
+        for name, calls, avg in rows:
+            fh.write(f'"{name}",{calls},{calls * avg},{avg},1.0,{avg},{avg}\n')
+
+
+def test_counter_table_aggregates_the_step(tmp_path):
+    """Bytes per launch = FETCH x scale_f + WRITE x scale_w; the step's aggregate counts every
+    hot-path launch, and the bf16 rounding only when the step rounds dC itself."""
+    kib = bench.COPY_BYTES / 1024.0
+    lk = "void fmm::line_kernel<3, float, float, float, float, 32, 1, 4, 2>(fmm::LineArgs)"
+    rnd = "fmm::(anonymous namespace)::f32_to_bf16_x8_kernel(HIP_vector_type<float, 4u> const*)"
+    cp = "__amd_rocclr_copyBuffer"
+    fetch = [(1, lk, 1000.0), (2, lk, 1000.0), (3, rnd, 100.0)] + [(10 + i, cp, kib / 2) for i in range(3)]
+    write = [(1, lk, 500.0), (2, lk, 500.0), (3, rnd, 50.0)] + [(10 + i, cp, kib) for i in range(3)]
+    for name in ("fused_f32", "fused_bf16_dc_bf16"):
+        _write_pmc(str(tmp_path / name / "f"), "FETCH_SIZE", fetch)
+        _write_pmc(str(tmp_path / name / "w"), "WRITE_SIZE", write)
+        _write_stats(str(tmp_path / name / "t"), [(lk, 2, 1000.0), (rnd, 1, 100.0)])
+    out = str(tmp_path / "c.md")
+    bench.counter_table(out, [f"{n}={tmp_path / n / 't'}:{tmp_path / n / 'f'}:{tmp_path / n / 'w'}"
+                              for n in ("fused_f32", "fused_bf16_dc_bf16")])
+    text = open(out).read()
+    per_launch = (1000.0 * 2 + 500.0) * 1024 / 1e6          # MB: FETCH scaled by 2, WRITE by 1
+    assert f"| {per_launch:.1f} |" in text
+    blocks = text.split("## ")
+    f32, dc16 = blocks[1], blocks[2]
+    # fused_f32 sums the two line-kernel launches only; the dC step adds the rounding launch
+    assert f"{2 * per_launch:.1f} (sum)" in f32
+    rounding = (100.0 * 2 + 50.0) * 1024 / 1e6
+    assert f"{2 * per_launch + rounding:.1f} (sum)" in dc16

@@ -268,3 +268,22 @@ def test_caller_buffers_are_checked():
             _check_buf("out", bad, cpu, torch.float32, (4, 3))
     with pytest.raises(ValueError):
         _check_buf("R_ws", torch.zeros(9), cpu, torch.float32, min_numel=10)
+
+
+def test_upstream_gradient_dtype_rules():
+    """Which upstream-gradient dtypes the adjoint wrappers take: the output dtype always; a
+    bfloat16 one only with bfloat16 storage and the fused adjoint."""
+    import torch
+
+    from paper_2203_07673_amd.fusedmm import _dc_flag
+    f32, bf16, f64 = (torch.zeros(1, dtype=d) for d in (torch.float32, torch.bfloat16, torch.float64))
+    assert _dc_flag(f32, C.FMM_F32, torch.float32, True) == 0
+    assert _dc_flag(f32, C.FMM_BF16, torch.float32, False) == 0
+    assert _dc_flag(bf16, C.FMM_BF16, torch.float32, True) == C.FMM_DC_BF16
+    assert _dc_flag(f64, C.FMM_F64, torch.float64, True) == 0
+    with pytest.raises(ValueError):
+        _dc_flag(bf16, C.FMM_BF16, torch.float32, False)  # the unfused adjoint reads dC as float32
+    for dc, code, odt in ((bf16, C.FMM_F32, torch.float32), (f64, C.FMM_F32, torch.float32),
+                          (f32, C.FMM_F64, torch.float64), (f64, C.FMM_BF16, torch.float32)):
+        with pytest.raises(TypeError):
+            _dc_flag(dc, code, odt, True)
