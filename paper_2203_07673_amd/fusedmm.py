@@ -822,11 +822,16 @@ def spmm_b(P: Pattern, A, w=None):
 
 def gat_scores(H, a1, a2):
     """s = H a1, t = H a2 (the two halves of the attention score a^T (H_i || H_j))."""
+    if not H.is_cuda or H.dim() != 2:
+        raise ValueError("H must be a 2-D GPU tensor")
     n, r = H.shape
     dcode = dtype_code(H)
     odt = _out_dtype(dcode)
     if a1.dtype != odt or a2.dtype != odt:
         raise TypeError(f"attention vectors must be {odt}")
+    for name, a in (("a1", a1), ("a2", a2)):
+        if a.device != H.device or a.numel() != r:
+            raise ValueError(f"{name} must hold r = {r} values on {H.device}")
     s = torch.empty(n, dtype=odt, device=H.device)
     t = torch.empty(n, dtype=odt, device=H.device)
     C.call("fmm_gat_scores", _ptr(H.contiguous()), n, r, dcode, _ptr(a1.contiguous()), _ptr(a2.contiguous()),
@@ -854,8 +859,8 @@ def gat_forward(P: Pattern, H, a1, a2, negative_slope=0.2, softmax=True, out=Non
         if ws is None:
             ws = torch.empty(nb.value, dtype=torch.uint8, device=P.device)
             P._ws_cache[("gat", nb.value)] = ws
-    if lse is not None and (lse.numel() != P.m or lse.dtype != odt or lse.device != P.device):
-        raise ValueError(f"lse must hold {P.m} {odt} values on {P.device}")
+    if lse is not None:
+        _check_buf("lse", lse, P.device, odt, (P.m,))
     C.call("fmm_gat_forward", ctypes.byref(P.csr), _ptr(s), _ptr(t), _ptr(H), r, dcode, float(negative_slope),
            C.FMM_GAT_SOFTMAX if softmax else 0, _ptr(out), _ptr(lse), _ptr(ws), nb.value, _stream())
     return out

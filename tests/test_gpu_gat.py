@@ -240,6 +240,14 @@ def test_gat_backward_bf16_upstream_gradient(case):
         F.gat_backward(P, dev(H), a1d, a2d, F.gat_forward(P, dev(H), a1d, a2d), dO16)
     with pytest.raises(TypeError):
         F.gat_backward(P, Hd, a1d, a2d, out.double(), dO16)
+    # attention vectors of the wrong length or device, and a misshapen lse, are refused
+    # before any launch
+    with pytest.raises(ValueError):
+        F.gat_forward(P, Hd, a1d[:-1], a2d)
+    with pytest.raises(ValueError):
+        F.gat_forward(P, Hd, a1d, a2d.cpu())
+    with pytest.raises(ValueError):
+        F.gat_forward(P, Hd, a1d, a2d, lse=torch.empty(S.m - 1, device="cuda"))
 
 
 @pytest.mark.parametrize("softmax", [True, False])
