@@ -987,6 +987,8 @@ def cg_lines(P: Pattern, orient, F, rhs, lam, iters, X):
     nmaj = P.m if orient == C.FMM_CSR else P.n
     r = F.shape[1]
     dcode = dtype_code(F)
+    # a line gathers F at its minor indices: F has a row per column (rows as lines) or per row
+    _check_dense("F", F, P.n if orient == C.FMM_CSR else P.m, r, P.device)
     _check_dense("X", X, nmaj, r, P.device)
     _check_dense("rhs", rhs, nmaj, r, P.device)
     if X.dtype != torch.float32 or rhs.dtype != torch.float32:
@@ -1008,6 +1010,10 @@ def als_residual(P: Pattern, A, B):
     as a float64 device scalar."""
     r = A.shape[1]
     dcode = dtype_code(A)
+    _check_dense("A", A, P.m, r, P.device)
+    _check_dense("B", B, P.n, r, P.device)
+    if B.dtype != A.dtype:
+        raise TypeError(f"A is {A.dtype} but B is {B.dtype}")
     nb = ctypes.c_size_t(0)
     C.call("fmm_residual_workspace", ctypes.byref(P.csr), ctypes.byref(nb))
     ws = P._ws_cache.get(("res", nb.value))

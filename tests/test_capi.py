@@ -287,3 +287,27 @@ def test_upstream_gradient_dtype_rules():
                           (f32, C.FMM_F64, torch.float64), (f64, C.FMM_BF16, torch.float32)):
         with pytest.raises(TypeError):
             _dc_flag(dc, code, odt, True)
+
+
+def test_als_helpers_check_shapes_before_calling():
+    """cg_lines gathers F at a line's minor indices and als_residual reads A and B by row
+    and column: misshapen operands are refused before any library call (a stand-in
+    pattern suffices, since nothing reaches the device)."""
+    import torch
+
+    class _Pattern:
+        m, n, device = 6, 5, torch.device("cpu")
+
+        def descriptor(self, orient):
+            return None
+
+    P = _Pattern()
+    x = torch.zeros(6, 4)
+    with pytest.raises(ValueError):  # rows as lines: F needs a row per column (5)
+        F.cg_lines(P, C.FMM_CSR, torch.zeros(6, 4), x, 1.0, 1, x.clone())
+    with pytest.raises(ValueError):  # columns as lines: F needs a row per row (6)
+        F.cg_lines(P, C.FMM_CSC, torch.zeros(5, 4), torch.zeros(5, 4), 1.0, 1, torch.zeros(5, 4))
+    with pytest.raises(ValueError):
+        F.als_residual(P, torch.zeros(6, 4), torch.zeros(6, 4))
+    with pytest.raises(TypeError):
+        F.als_residual(P, torch.zeros(6, 4), torch.zeros(5, 4, dtype=torch.float64))
