@@ -1,0 +1,87 @@
+"""Property-based pins for the FP64 oracle (hypothesis, derandomized so every run checks
+the same cases): on random small patterns, empty ones included, the oracle agrees with
+dense brute force for FusedMMA and FusedMMB (Section II); its CSR -> CSC conversion is
+the dense transpose and round-trips; and its adjoint satisfies the directional
+derivative identity <dA, V> + <dB, W> = d/dt <G, FusedMMA(S, A + tV, B + tW)> at t = 0,
+where the five-point central difference is exact up to rounding (the loss is a
+polynomial of degree <= 3 in t: linear in A, quadratic in B)."""
+import numpy as np
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+import oracle
+from workloads import CsrPattern
+
+SETTINGS = settings(max_examples=200, deadline=None, derandomize=True)
+
+
+@st.composite
+def problems(draw):
+    m = draw(st.integers(1, 9))
+    n = draw(st.integers(1, 9))
+    r = draw(st.integers(1, 5))
+    seed = draw(st.integers(0, 2 ** 31 - 1))
+    density = draw(st.sampled_from([0.0, 0.2, 0.5, 1.0]))
+    rng = np.random.default_rng(seed)
+    mask = rng.random((m, n)) < density
+    rows, cols = np.nonzero(mask)  # row-major order: CSR with increasing columns per row
+    rowptr = np.zeros(m + 1, np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    val = rng.uniform(-1.0, 1.0, rows.size)
+    S = CsrPattern(m, n, rowptr, cols.astype(np.int32), val)
+    A = rng.standard_normal((m, r))
+    B = rng.standard_normal((n, r))
+    G = rng.standard_normal((m, r))
+    return S, A, B, G, rng
+
+
+def _dense(S):
+    D = np.zeros((S.m, S.n))
+    rows = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    D[rows, S.colidx] = S.val
+    return D
+
+
+def _close(got, want, tol=1e-11):
+    got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
+    assert got.shape == want.shape
+    if got.size:
+        scale = max(1.0, float(np.abs(want).max()))
+        assert float(np.abs(got - want).max()) <= tol * scale
+
+
+@SETTINGS
+@given(problems())
+def test_fusedmm_matches_dense_bruteforce(p):
+    S, A, B, _, _ = p
+    R = _dense(S) * (A @ B.T)  # the sampled product, zero off the pattern
+    _close(oracle.fusedmm_a(S, A, B), R @ B)
+    _close(oracle.fusedmm_b(S, A, B), R.T @ A)
+
+
+@SETTINGS
+@given(problems())
+def test_transpose_is_dense_transpose_and_round_trips(p):
+    S, _, _, _, _ = p
+    ST = oracle.transpose(S)
+    assert (ST.m, ST.n) == (S.n, S.m)
+    _close(_dense(ST), _dense(S).T, tol=0.0)
+    back = oracle.transpose(ST)
+    assert np.array_equal(back.rowptr, S.rowptr) and np.array_equal(back.colidx, S.colidx)
+    assert np.array_equal(back.val, S.val)
+
+
+@SETTINGS
+@given(problems())
+def test_adjoint_directional_derivative(p):
+    S, A, B, G, rng = p
+    V, W = rng.standard_normal(A.shape), rng.standard_normal(B.shape)
+    dA, dB = oracle.fusedmm_a_backward(S, A, B, G)
+    lhs = float(np.sum(dA * V) + np.sum(dB * W))
+
+    def loss(t):
+        return float(np.sum(G * oracle.fusedmm_a(S, A + t * V, B + t * W)))
+    h = 0.5  # d/dt at 0 from values at +-h and +-2h: the five-point stencil, exact for cubics
+    rhs = (8 * (loss(h) - loss(-h)) - (loss(2 * h) - loss(-2 * h))) / (12 * h)
+    assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs), abs(rhs))
