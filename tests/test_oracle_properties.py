@@ -85,3 +85,20 @@ def test_adjoint_directional_derivative(p):
     h = 0.5  # d/dt at 0 from values at +-h and +-2h: the five-point stencil, exact for cubics
     rhs = (8 * (loss(h) - loss(-h)) - (loss(2 * h) - loss(-2 * h))) / (12 * h)
     assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs), abs(rhs))
+
+
+@SETTINGS
+@given(problems())
+def test_value_gradient_is_exact_difference(p):
+    """<G, FusedMMA(S, A, B)> is linear in S's stored values, so <dS, D> equals the plain
+    difference of the loss along D (and the same for FusedMMB with an n x r gradient)."""
+    S, A, B, G, rng = p
+    D = rng.standard_normal(S.val.shape)
+    Sd = CsrPattern(S.m, S.n, S.rowptr, S.colidx, S.val + D)
+    for form, fwd, grad, Gf in (("a", oracle.fusedmm_a, oracle.fusedmm_a_backward_values, G),
+                                ("b", oracle.fusedmm_b, oracle.fusedmm_b_backward_values,
+                                 rng.standard_normal((S.n, A.shape[1])))):
+        dS = grad(S, A, B, Gf)
+        lhs = float(np.sum(dS * D))
+        rhs = float(np.sum(Gf * fwd(Sd, A, B)) - np.sum(Gf * fwd(S, A, B)))
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs), abs(rhs)), form
