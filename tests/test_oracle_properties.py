@@ -102,3 +102,34 @@ def test_value_gradient_is_exact_difference(p):
         lhs = float(np.sum(dS * D))
         rhs = float(np.sum(Gf * fwd(Sd, A, B)) - np.sum(Gf * fwd(S, A, B)))
         assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs), abs(rhs)), form
+
+
+@SETTINGS
+@given(problems())
+def test_primitive_adjoints_are_transposes(p):
+    """Each primitive is linear in every argument, so its adjoint is exact against the
+    forward along random directions (the dot-product test <y, J x> = <J^T y, x>)."""
+    S, A, B, G, rng = p
+    r = A.shape[1]
+    nnz = S.val.shape[0]
+    dR = rng.standard_normal(nnz)
+    w = rng.standard_normal(nnz)
+    Gb = rng.standard_normal((S.n, r))
+    V, W, dw = rng.standard_normal(A.shape), rng.standard_normal(B.shape), rng.standard_normal(nnz)
+
+    def check(lhs, rhs):
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs), abs(rhs))
+    # SDDMM: bilinear in (A, B); the loss <dR, R> is quadratic, so a central difference is exact
+    gA, gB = oracle.sddmm_backward(S, A, B, dR)
+
+    def sd(t):
+        return float(np.sum(dR * oracle.sddmm(S, A + t * V, B + t * W)))
+    check(float(np.sum(gA * V) + np.sum(gB * W)), (sd(0.5) - sd(-0.5)) / 1.0)
+    # SpMMA: C = W(w) B, linear in w and in B
+    gw, gB = oracle.spmm_a_backward(S, w, B, G)
+    check(float(np.sum(gw * dw)), float(np.sum(G * oracle.spmm_a(S, dw, B))))
+    check(float(np.sum(gB * W)), float(np.sum(G * oracle.spmm_a(S, w, W))))
+    # SpMMB: C' = W(w)^T A, linear in w and in A
+    gw, gA = oracle.spmm_b_backward(S, w, A, Gb)
+    check(float(np.sum(gw * dw)), float(np.sum(Gb * oracle.spmm_b(S, dw, A))))
+    check(float(np.sum(gA * V)), float(np.sum(Gb * oracle.spmm_b(S, w, V))))
