@@ -2,7 +2,7 @@
 the same cases): on random small patterns, empty ones included, the oracle agrees with
 dense brute force for FusedMMA and FusedMMB (Section II); its CSR -> CSC conversion is
 the dense transpose and round-trips; and its adjoint satisfies the directional
-derivative identity <dA, V> + <dB, W> = d/dt <G, FusedMMA(S, A + tV, B + tW)> at t = 0,
+derivative identity <dA, V> + <dB, W> = d/dt <G, FusedMM(S, A + tV, B + tW)> at t = 0,
 where the five-point central difference is exact up to rounding (the loss is a
 polynomial of degree <= 3 in t: linear in A, quadratic in B)."""
 import numpy as np
@@ -77,14 +77,17 @@ def test_transpose_is_dense_transpose_and_round_trips(p):
 def test_adjoint_directional_derivative(p):
     S, A, B, G, rng = p
     V, W = rng.standard_normal(A.shape), rng.standard_normal(B.shape)
-    dA, dB = oracle.fusedmm_a_backward(S, A, B, G)
-    lhs = float(np.sum(dA * V) + np.sum(dB * W))
+    Gb = rng.standard_normal((S.n, A.shape[1]))
+    for fwd, bwd, Gf in ((oracle.fusedmm_a, oracle.fusedmm_a_backward, G),
+                         (oracle.fusedmm_b, oracle.fusedmm_b_backward, Gb)):
+        dA, dB = bwd(S, A, B, Gf)
+        lhs = float(np.sum(dA * V) + np.sum(dB * W))
 
-    def loss(t):
-        return float(np.sum(G * oracle.fusedmm_a(S, A + t * V, B + t * W)))
-    h = 0.5  # d/dt at 0 from values at +-h and +-2h: the five-point stencil, exact for cubics
-    rhs = (8 * (loss(h) - loss(-h)) - (loss(2 * h) - loss(-2 * h))) / (12 * h)
-    assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs), abs(rhs))
+        def loss(t):
+            return float(np.sum(Gf * fwd(S, A + t * V, B + t * W)))
+        h = 0.5  # d/dt at 0 from values at +-h and +-2h: the five-point stencil, exact for cubics
+        rhs = (8 * (loss(h) - loss(-h)) - (loss(2 * h) - loss(-2 * h))) / (12 * h)
+        assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs), abs(rhs)), fwd.__name__
 
 
 @SETTINGS
