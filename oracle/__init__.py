@@ -347,11 +347,6 @@ def gat_forward(S, H, a1, a2, slope=0.2, softmax=True, use_val=True, rows=None):
     return spmm_a(S, w, H, rows=rows)
 
 
-# ----------------------------------------------------------------------------------
-# Alternating least squares (Section VI-E): batched CG on the per-line normal equations
-# ----------------------------------------------------------------------------------
-
-
 def gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True, use_val=True):
     """Adjoint of the attention head out = W H (the paper gives the forward only; this is
     the chain rule through its definition, step by step).  With upstream gradient dO:
@@ -393,6 +388,12 @@ def gat_backward(S, H, a1, a2, dO, slope=0.2, softmax=True, use_val=True):
     da2 = H.T @ dt
     dS = dx * score if use_val and S.val is not None else None
     return dH, da1, da2, dS
+
+
+# ----------------------------------------------------------------------------------
+# Alternating least squares (Section VI-E): batched CG on the per-line normal equations
+# ----------------------------------------------------------------------------------
+
 
 def gram_apply(S, X, F):
     """Per line i of S's pattern: sum_j <X_i, F_j> F_j (S's values ignored)."""

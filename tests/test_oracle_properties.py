@@ -136,3 +136,45 @@ def test_primitive_adjoints_are_transposes(p):
     gw, gA = oracle.spmm_b_backward(S, w, A, Gb)
     check(float(np.sum(gw * dw)), float(np.sum(Gb * oracle.spmm_b(S, dw, A))))
     check(float(np.sum(gA * V)), float(np.sum(Gb * oracle.spmm_b(S, w, V))))
+
+
+@st.composite
+def attention_problems(draw):
+    n = draw(st.integers(1, 7))
+    r = draw(st.integers(1, 4))
+    seed = draw(st.integers(0, 2 ** 31 - 1))
+    density = draw(st.sampled_from([0.3, 0.6, 1.0]))
+    softmax = draw(st.booleans())
+    rng = np.random.default_rng(seed)
+    rows, cols = np.nonzero(rng.random((n, n)) < density)
+    rowptr = np.cumsum(np.concatenate([[0], np.bincount(rows, minlength=n)])).astype(np.int32)
+    S = CsrPattern(n, n, rowptr, cols.astype(np.int32), rng.uniform(0.5, 1.5, rows.size))
+    return S, rng.standard_normal((n, r)), rng.standard_normal(r), rng.standard_normal(r), \
+        rng.standard_normal((n, r)), softmax, rng
+
+
+@SETTINGS
+@given(attention_problems())
+def test_attention_adjoint_directional_derivative(p):
+    """The attention head's adjoint (dH, da1, da2, dS) against a five-point central
+    difference of <dO, out> along random directions in H, a1, a2 and S's values.  The head
+    is smooth away from LeakyReLU's kink, so examples with a score within reach of 0 are
+    skipped."""
+    from hypothesis import assume
+
+    S, H, a1, a2, dO, softmax, rng = p
+    h = 1e-3
+    V, u1, u2 = rng.standard_normal(H.shape), rng.standard_normal(a1.shape), rng.standard_normal(a2.shape)
+    dv = rng.standard_normal(S.val.shape)
+    s, t = oracle.gat_scores(H, a1, a2)
+    rows = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    x = S.val * (s[rows] + t[S.colidx])
+    assume(x.size == 0 or np.min(np.abs(x)) > 0.05)
+    dH, da1, da2, dS = oracle.gat_backward(S, H, a1, a2, dO, softmax=softmax)
+    lhs = float(np.sum(dH * V) + np.sum(da1 * u1) + np.sum(da2 * u2) + np.sum(dS * dv))
+
+    def loss(e):
+        St = CsrPattern(S.m, S.n, S.rowptr, S.colidx, S.val + e * dv)
+        return float(np.sum(dO * oracle.gat_forward(St, H + e * V, a1 + e * u1, a2 + e * u2, softmax=softmax)))
+    rhs = (8 * (loss(h) - loss(-h)) - (loss(2 * h) - loss(-2 * h))) / (12 * h)
+    assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(lhs)), (lhs, rhs)
