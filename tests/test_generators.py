@@ -1,5 +1,7 @@
 """Seeded synthetic inputs: determinism and structural properties."""
 import numpy as np
+from hypothesis import given, settings
+from hypothesis import strategies as st
 
 from workloads import batch_er, content_hash, dense_normal, er_exact_degree, rmat, workload
 
@@ -64,3 +66,36 @@ def test_dense_normal_sigma_and_workload_shapes():
     assert w["S"].nnz == 131072 and w["A"].shape == (4096, 32) and w["B"].shape == (4096, 32)
     w = workload("fd256_d8_r8", dtype=np.float64)
     assert w["S"].nnz == 2048 and w["A"].dtype == np.float64 and w["S"].val.dtype == np.float64
+
+
+_PROPS = settings(max_examples=80, deadline=None, derandomize=True)
+
+
+@_PROPS
+@given(st.integers(1, 40), st.integers(1, 60), st.data())
+def test_er_exact_degree_properties(m, n, data):
+    """Any (m, n, d <= n, seed): exactly d distinct, strictly increasing, in-range columns
+    per row, values in [0, 1), and the same seed gives the same matrix."""
+    d = data.draw(st.integers(0, n))
+    seed = data.draw(st.integers(0, 2 ** 31 - 1))
+    S = er_exact_degree(m, n, d, seed=seed)
+    assert np.array_equal(np.diff(S.rowptr), np.full(m, d))
+    cols = S.colidx.reshape(m, d) if d else np.zeros((m, 0), np.int32)
+    assert (np.diff(cols, axis=1) > 0).all() and ((cols >= 0) & (cols < n)).all()
+    assert ((S.val >= 0) & (S.val < 1)).all()
+    T = er_exact_degree(m, n, d, seed=seed)
+    assert np.array_equal(T.colidx, S.colidx) and np.array_equal(T.val, S.val)
+
+
+@_PROPS
+@given(st.integers(1, 9), st.integers(1, 8), st.integers(0, 2 ** 31 - 1))
+def test_rmat_properties(scale, ef, seed):
+    """Any small R-MAT: a canonical CSR (strictly increasing columns, no duplicates) on
+    2**scale vertices with at most ef * 2**scale entries."""
+    S = rmat(scale, ef, seed=seed)
+    n = 1 << scale
+    assert S.m == S.n == n and S.rowptr[0] == 0 and S.rowptr[-1] == S.colidx.size <= ef * n
+    assert (np.diff(S.rowptr) >= 0).all() and ((S.colidx >= 0) & (S.colidx < n)).all()
+    for i in range(n):
+        row = S.colidx[S.rowptr[i]:S.rowptr[i + 1]]
+        assert (np.diff(row) > 0).all()
