@@ -13,6 +13,8 @@ from paper_2203_07673_amd import _capi as C
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIP_INCLUDE = "/opt/rocm/include"
+needs_toolchain = pytest.mark.skipif(shutil.which("gcc") is None or not os.path.isdir(HIP_INCLUDE),
+                                     reason="needs gcc and the HIP headers")
 
 STRUCTS = {"fmm_sparse": C.fmm_sparse, "fmm_batch_graph": C.fmm_batch_graph, "fmm_batch_info": C.fmm_batch_info}
 CONSTANTS = ["FMM_ABI_VERSION", "FMM_OK", "FMM_F32", "FMM_BF16", "FMM_F64", "FMM_CSR", "FMM_CSC", "FMM_FUSED",
@@ -44,7 +46,7 @@ def _program():
     return "\n".join(lines) + "\n"
 
 
-@pytest.mark.skipif(shutil.which("gcc") is None or not os.path.isdir(HIP_INCLUDE), reason="needs gcc and HIP headers")
+@needs_toolchain
 def test_header_is_c_and_matches_the_binding(tmp_path):
     lib_dir = os.path.dirname(C.LIB_PATH)
     src = tmp_path / "abi.c"
@@ -69,3 +71,17 @@ def test_header_is_c_and_matches_the_binding(tmp_path):
     assert int(got[("call", "null")]) == -1
     assert int(got[("call", "orient")]) == -4   # a CSC descriptor where CSR is required
     assert got[("call", "status")] == C.status_string(-7)
+
+
+@needs_toolchain
+def test_readme_c_example_compiles(tmp_path):
+    """The C example in README.md is real code: it compiles as C11 against include/fmm.h
+    with every warning an error (compiled only; it would need a GPU to run)."""
+    text = open(os.path.join(ROOT, "README.md")).read()
+    blocks = text.split("```c\n")
+    assert len(blocks) == 2, "README.md holds one C example"
+    src = tmp_path / "example.c"
+    src.write_text(blocks[1].split("```", 1)[0])
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-Wno-unused-parameter",
+                    "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", f"-I{HIP_INCLUDE}", "-c", str(src),
+                    "-o", str(tmp_path / "example.o")], check=True, capture_output=True, text=True)
