@@ -19,7 +19,8 @@ needs_toolchain = pytest.mark.skipif(shutil.which("gcc") is None or not os.path.
 STRUCTS = {"fmm_sparse": C.fmm_sparse, "fmm_batch_graph": C.fmm_batch_graph, "fmm_batch_info": C.fmm_batch_info}
 CONSTANTS = ["FMM_ABI_VERSION", "FMM_OK", "FMM_F32", "FMM_BF16", "FMM_F64", "FMM_CSR", "FMM_CSC", "FMM_FUSED",
              "FMM_UNFUSED", "FMM_DC_BF16", "FMM_VARIANT_AUTO", "FMM_VARIANT_DEEP", "FMM_VARIANT_MEDIUM",
-             "FMM_VARIANT_SHALLOW", "FMM_BATCH_FWD", "FMM_BATCH_DC_BF16", "FMM_BATCH_BWD", "FMM_GAT_SOFTMAX", "FMM_OP_SDDMM", "FMM_OP_SPMM_A", "FMM_OP_SPMM_B",
+             "FMM_VARIANT_SHALLOW", "FMM_BATCH_FWD", "FMM_BATCH_DC_BF16", "FMM_BATCH_BWD", "FMM_GAT_SOFTMAX",
+             "FMM_OP_SDDMM", "FMM_OP_SPMM_A", "FMM_OP_SPMM_B",
              "FMM_OP_FUSEDMM_A", "FMM_OP_FUSEDMM_B", "FMM_OP_FUSEDMM_A_BWD", "FMM_OP_FUSEDMM_B_BWD",
              "FMM_OP_SDDMM_BWD", "FMM_OP_SPMM_A_BWD", "FMM_OP_SPMM_B_BWD", "FMM_OP_FUSEDMM_A_BWD_VALUES",
              "FMM_OP_FUSEDMM_B_BWD_VALUES"]
@@ -37,8 +38,8 @@ def _program():
         "    fmm_sparse d = {0};",
         "    d.orient = FMM_CSC; d.rows = 4; d.cols = 5; d.nnz = 6;",
         '    printf("call abi %d\\n", (int)fmm_abi_version());',
-        '    printf("call null %d\\n", (int)fmm_fusedmm_a(NULL, NULL, NULL, 32, FMM_F32, NULL, FMM_FUSED, NULL, NULL, 0,'
-        ' NULL));',
+        '    printf("call null %d\\n", (int)fmm_fusedmm_a(NULL, NULL, NULL, 32, FMM_F32, NULL, FMM_FUSED, NULL,'
+        ' NULL, 0, NULL));',
         '    printf("call orient %d\\n", (int)fmm_fusedmm_a(&d, (void *)16, (void *)16, 32, FMM_F32, (void *)16,'
         ' FMM_FUSED, NULL, NULL, 0, NULL));',
         '    printf("call status %s\\n", fmm_status_string(FMM_ERR_WORKSPACE));',
