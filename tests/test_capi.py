@@ -311,3 +311,34 @@ def test_als_helpers_check_shapes_before_calling():
         F.als_residual(P, torch.zeros(6, 4), torch.zeros(6, 4))
     with pytest.raises(TypeError):
         F.als_residual(P, torch.zeros(6, 4), torch.zeros(5, 4, dtype=torch.float64))
+
+
+def test_raw_wrappers_refuse_bad_buffers_before_calling():
+    """The raw wrappers check shapes, dtypes and caller-supplied buffers before touching
+    the library; a stand-in pattern (no descriptor, no workspace) shows that nothing is
+    called when a check fails."""
+    import torch
+
+    class _Pattern:
+        m, n, nnz, device = 6, 5, 9, torch.device("cpu")
+        val, val_dtype = torch.zeros(9), torch.float32
+
+    P = _Pattern()
+    A, B, G = torch.zeros(6, 4), torch.zeros(5, 4), torch.zeros(6, 4)
+    cases = [
+        (lambda: F.fusedmm_a_raw(P, A, B, out=torch.zeros(5, 4)), ValueError),
+        (lambda: F.fusedmm_a_raw(P, A, B, out=torch.zeros(6, 4, dtype=torch.float64)), TypeError),
+        (lambda: F.fusedmm_a_raw(P, A, B, fused=False, R_ws=torch.zeros(8)), ValueError),
+        (lambda: F.fusedmm_b_raw(P, A, B, out=torch.zeros(6, 4)), ValueError),
+        (lambda: F.fusedmm_a_raw(P, A, torch.zeros(5, 4, dtype=torch.float64)), TypeError),
+        (lambda: F.fusedmm_a_backward_raw(P, A, B, G, dA=torch.zeros(6, 3)), ValueError),
+        (lambda: F.fusedmm_a_backward_raw(P, A, B, G.double()), TypeError),
+        (lambda: F.fusedmm_b_backward_raw(P, A, B, torch.zeros(6, 4)), ValueError),   # dC is n x r here
+        (lambda: F.fusedmm_a_backward_values_raw(P, A, B, G, dS=torch.zeros(8)), ValueError),
+        (lambda: F.sddmm_raw(P, A, B, out=torch.zeros(8)), ValueError),
+        (lambda: F.spmm_a_raw(P, B, w=torch.zeros(8)), ValueError),
+        (lambda: F.spmm_b_raw(P, A, out=torch.zeros(5, 4).t()), ValueError),
+    ]
+    for k, (call, exc) in enumerate(cases):
+        with pytest.raises(exc):
+            call()
