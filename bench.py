@@ -3,12 +3,17 @@
 One step = C = FusedMMA(S, A, B) (fused), then the adjoint for the loss sum(C * G):
 dA (row pass over the CSR) and dB (column pass over the stored transpose).  Inputs
 are seeded synthetic data resident in HBM before timing starts.  The default
-workload is Erdos-Renyi S 2^20 x 2^20 with 32 nonzeros per row, r = 128, float32.
+workload is R-MAT scale 22 (4,194,304 vertices, edge factor 16, duplicates removed:
+65.2M stored entries with power-law row and column lengths), r = 256, float32; the
+paper's skewed real-world matrices are not available and this stands in for them.
 
 Prints one JSON line with the step throughput (GFLOP/s, counting 12 r nnz flops per
 step as the paper counts SDDMM and SpMM at 2 r nnz each), the roofline entry of the
-dominant kernel (timed with HIP events on the launch stream), side measurements
-(unfused float32 and fused bfloat16 steps, FusedMMB) and the CPU oracle baseline.
+dominant kernel (timed with HIP events on the launch stream; its fraction of the HBM
+peak under the gather, compulsory and counter byte counts), side measurements (unfused
+float32 and fused bfloat16 steps, FusedMMB), and the oracle leg: the error of every
+output of each variant against the FP64 oracle on sampled lines, and the oracle's own
+throughput on the host's cores.
 """
 import argparse
 import json
@@ -86,49 +91,136 @@ def als_sweep_bytes(m, n, nnz, r, cg_steps=10):
     return side(m) + side(n)
 
 
-def cpu_baseline(w, target_s=15.0, single_s=6.0):
-    """The FP64 oracle (fwd + adjoint) on the first K rows of the same workload, with all
-    of the host's threads (the reported value) and with one thread."""
-    from types import SimpleNamespace
+def sample_lines(ptr, k, seed):
+    """A seeded sample of lines for the error report: k random lines, the 16 longest (split
+    lines on R-MAT) and up to 8 empty ones, sorted and unique."""
+    lens = np.diff(np.asarray(ptr, dtype=np.int64))
+    rng = np.random.default_rng(seed)
+    rand = rng.choice(lens.shape[0], size=min(k, lens.shape[0]), replace=False)
+    longest = np.argsort(lens, kind="stable")[-16:]
+    empty = np.flatnonzero(lens == 0)[:8]
+    return np.unique(np.concatenate([rand, longest, empty])).astype(np.int64)
 
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, target_s=5.0, single_s=3.0, reps=3):
+    """The FP64 oracle (FusedMMA forward + adjoint) timed on the first K rows of the same
+    workload: its -O3 -march=native build (same source and arithmetic as the parity build),
+    with all of the host's threads (the reported value) and with one thread, median of
+    `reps` runs each.  Only the rows of A, B and G the sample touches are promoted to
+    float64 (restrict_rows), outside the timed region."""
+    import oracle
+
+    S, r = w["S"], w["r"]
+    oracle.select_build("native")
+
+    def prep(K):
+        Sk, cols = oracle.restrict_rows(S, np.arange(K))
+        return (Sk, np.ascontiguousarray(w["A"][:K], dtype=np.float64),
+                np.ascontiguousarray(w["B"][cols], dtype=np.float64),
+                np.ascontiguousarray(w["G"][:K], dtype=np.float64))
+
+    def run(args):
+        Sk, Ak, Bk, Gk = args
+        t0 = time.perf_counter()
+        oracle.fusedmm_a(Sk, Ak, Bk)
+        oracle.fusedmm_a_backward(Sk, Ak, Bk, Gk)
+        return time.perf_counter() - t0
+
+    def sample(K, target):
+        # grow the row sample until one run takes at least half the target time, then
+        # take the median of `reps` runs
+        args = prep(K)
+        t = run(args)
+        while t < 0.5 * target and K < S.m:
+            K = int(min(S.m, max(2 * K, K * target / max(t, 1e-3))))
+            args = prep(K)
+            t = run(args)
+        ts = [t] + [run(args) for _ in range(reps - 1)]
+        return K, float(np.median(ts)), ts, int(S.rowptr[K])
+
+    threads = oracle.num_threads()
+    K, t, ts, nz = sample(min(S.m, 8192), target_s)
+    oracle.set_num_threads(1)
+    try:
+        K1, t1, ts1, nz1 = sample(min(S.m, 1024), single_s)
+    finally:
+        oracle.set_num_threads(threads)
+    oracle.select_build("default")
+    runs = lambda x: ", ".join(f"{v:.2f}" for v in x)  # noqa: E731
+    return {"value": round(12.0 * r * nz / t / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "build": "gcc " + oracle.build_flags("native"),
+            "sample": f"first {K} of {S.m} rows ({nz} nonzeros), FusedMMA forward + adjoint in float64, "
+                      f"median of {len(ts)} runs ({runs(ts)} s)",
+            "single_thread": {"value": round(12.0 * r * nz1 / t1 / 1e9, 3), "cores": 1,
+                              "sample": f"first {K1} rows ({nz1} nonzeros), median of {len(ts1)} runs "
+                                        f"({runs(ts1)} s)"}}
+
+
+def error_report(w, outputs, rows, cols):
+    """Error of every output of each measured step variant against the FP64 oracle, on the
+    sampled rows of C and dA and the sampled columns of dB (exact for those outputs: lines
+    are independent).  For each output: componentwise max |x - ref| / mag, with mag the
+    oracle on absolute values (the gate of the parity tests), and normwise
+    ||x - ref||_F / ||ref||_F.  bfloat16 variants are compared with the oracle on the
+    float32 inputs (storage error included) and on the bf16-rounded inputs (accumulation
+    error alone)."""
     import oracle
 
     S = w["S"]
-    r = w["r"]
-    A = np.ascontiguousarray(w["A"], dtype=np.float64)
-    B = np.ascontiguousarray(w["B"], dtype=np.float64)
-    G = np.ascontiguousarray(w["G"], dtype=np.float64)
+    ST = oracle.transpose(S)
+    SA, STA = oracle.absolute(S), oracle.absolute(ST)
+    A, B, G = w["A"], w["B"], w["G"]
+    rnd, ab = oracle.bf16_round, np.abs
+    rab = lambda x: np.abs(oracle.bf16_round(x))  # noqa: E731
+    refs = {}
 
-    def run(K):
-        nz = int(S.rowptr[K])
-        Sk = SimpleNamespace(m=K, n=S.n, rowptr=S.rowptr[:K + 1], colidx=S.colidx[:nz],
-                             val=np.ascontiguousarray(S.val[:nz], dtype=np.float64))
-        t0 = time.perf_counter()
-        oracle.fusedmm_a(Sk, A[:K], B)
-        oracle.fusedmm_a_backward(Sk, A[:K], B, G[:K])
-        return time.perf_counter() - t0, nz
+    def ref(kind):
+        if kind not in refs:
+            pa, pg = {"f32": ((None, None, None), (ab, ab, ab)),
+                      "bf16": ((rnd, rnd, None), (rab, rab, ab)),
+                      "bf16_dc": ((rnd, rnd, rnd), (rab, rab, rab))}[kind]
+            refs[kind] = (oracle.fusedmm_a_outputs_sampled(S, ST, A, B, G, rows, cols, prep=pa),
+                          oracle.fusedmm_a_outputs_sampled(SA, STA, A, B, G, rows, cols, prep=pg))
+        return refs[kind]
 
-    def sample(K, target):
-        # grow the row sample until the timed run takes at least half the target time
-        t, nz = run(K)
-        while t < 0.5 * target and K < S.m:
-            K = int(min(S.m, max(2 * K, K * target / max(t, 1e-3))))
-            t, nz = run(K)
-        return K, t, nz
+    def errs(got, kind):
+        (rC, rA, rB), (mC, mA, mB) = ref(kind)
+        out = {}
+        for name, x, r, m in (("C", got[0], rC, mC), ("dA", got[1], rA, mA), ("dB", got[2], rB, mB)):
+            zero = m == 0
+            comp = float("inf") if np.any(x[zero] != 0) else \
+                float(np.max(np.abs(x - r)[~zero] / m[~zero], initial=0.0))
+            den = np.linalg.norm(r)
+            out[name] = {"componentwise": float(f"{comp:.3e}"),
+                         "normwise": float(f"{(np.linalg.norm(x - r) / den if den > 0 else 0.0):.3e}")}
+        return out
 
-    threads = oracle.num_threads()
-    K, t, nz = sample(min(S.m, 8192), target_s)
-    oracle.set_num_threads(1)
-    try:
-        K1, t1, nz1 = sample(min(S.m, 1024), single_s)
-    finally:
-        oracle.set_num_threads(threads)
-    gflops = 12.0 * r * nz / t / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {K} of {S.m} rows ({nz} nonzeros), FusedMMA forward + adjoint in float64, "
-                      f"{t:.1f} s, one run",
-            "single_thread": {"value": round(12.0 * r * nz1 / t1 / 1e9, 3), "cores": 1,
-                              "sample": f"first {K1} rows ({nz1} nonzeros), {t1:.1f} s, one run"}}
+    rep = {"sample": f"{rows.size} rows of C and dA, {cols.size} columns of dB (random, the 16 longest, "
+                     f"empty ones); seeded",
+           "gate": {"f32": 1e-5, "bf16_storage": 2e-2},
+           "measure": "componentwise max|x-ref|/mag (mag: the oracle on absolute values); normwise "
+                      "||x-ref||_F/||ref||_F"}
+    for v, got in outputs.items():
+        if v.startswith("fused_bf16"):
+            kind = "bf16_dc" if v.endswith("dc_bf16") else "bf16"
+            rep[v] = {"vs_f32_inputs": errs(got, "f32"), "vs_bf16_rounded_inputs": errs(got, kind)}
+            rep[v]["within_gate"] = all(x["componentwise"] <= 2e-2 for x in rep[v]["vs_f32_inputs"].values())
+        else:
+            rep[v] = errs(got, "f32")
+            rep[v]["within_gate"] = all(x["componentwise"] <= 1e-5 for x in rep[v].values() if isinstance(x, dict))
+    return rep
+
 
 COPY_BYTES = 1 << 30
 # the sources that define the line kernels (their counters go stale when these change)
@@ -738,7 +830,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="er1m_d32_r128")
+    ap.add_argument("--workload", default="rmat22_ef16_r256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -860,6 +952,17 @@ def main():
     step_ms = []
     t_step, kt = time_steps(step_f32, args.steps, args.warmup, step_ms=step_ms)
     gflops = flops / t_step / 1e9
+    # sampled outputs of the last timed step of each variant, for the error report
+    colptr_h = np.concatenate([[0], np.cumsum(np.bincount(S.colidx, minlength=n))])
+    rows_s, cols_s = sample_lines(S.rowptr, 1024, 7), sample_lines(colptr_h, 1024, 8)
+    rows_d, cols_d = torch.from_numpy(rows_s).to(dev), torch.from_numpy(cols_s).to(dev)
+    outputs = {}
+
+    def keep(name):
+        torch.cuda.synchronize()
+        outputs[name] = tuple(x.index_select(0, i).double().cpu().numpy()
+                              for x, i in ((C, rows_d), (dA, rows_d), (dB, cols_d)))
+    keep("fused_f32")
     log(f"fused f32 step {t_step * 1e3:.3f} ms -> {gflops:.1f} GFLOP/s; kernels (ms) {kt}")
 
     e = 4
@@ -890,8 +993,12 @@ def main():
                            "bwd_col": "adjoint column pass dB"}[dom] + f" ({kernel_key})",
                 "kernel_ms": round(kt[dom], 4), "bytes_per_launch": int(dom_bytes),
                 "bytes_model": "gather (each stored entry fetches its dense row(s))",
+                "frac_gather_model": round(achieved / HBM_PEAK_GBS, 4),
                 "frac_compulsory_bytes": round(kernel_bytes_min(dom, m, n, nnz, r, e) / (kt[dom] * 1e-3) / 1e9
                                                / HBM_PEAK_GBS, 4),
+                "bytes_compulsory": int(kernel_bytes_min(dom, m, n, nnz, r, e)),
+                "frac_counters": None if traffic is None else
+                round(traffic / (kt[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "step_traffic": None if step_traffic is None else int(step_traffic),
                 "step_traffic_frac": None if step_traffic is None else
                 round(step_traffic / (sum(kt.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -902,6 +1009,7 @@ def main():
         R_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
         dP_ws = torch.empty(nnz, dtype=torch.float32, device=dev)
         t_unf, kt_unf = time_steps(make_step(A, B, fused=False, R_ws=R_ws, dP_ws=dP_ws), vsteps, 2)
+        keep("unfused_f32")
         variants["unfused_f32"] = {"ms_per_step": round(t_unf * 1e3, 4), "gflops": round(flops / t_unf / 1e9, 1),
                                    "kernel_ms": {k: round(v, 4) for k, v in kt_unf.items()}}
         log(f"unfused f32 step {t_unf * 1e3:.3f} ms")
@@ -909,6 +1017,7 @@ def main():
         A16, B16 = F.to_bf16(A), F.to_bf16(B)
         P.autotune(A16, B16, G, form="a")
         t_bf, kt_bf = time_steps(make_step(A16, B16, fused=True), vsteps, 2)
+        keep("fused_bf16")
         variants["fused_bf16"] = {"ms_per_step": round(t_bf * 1e3, 4), "gflops": round(flops / t_bf / 1e9, 1),
                                   "kernel_ms": {k: round(v, 4) for k, v in kt_bf.items()},
                                   "tuning_arg": tuning_arg(P.tuning)}
@@ -916,6 +1025,7 @@ def main():
 
         # bfloat16 upstream gradient as well (rounded inside the timed step)
         t_bg, kt_bg = time_steps(make_step(A16, B16, fused=True, dc_bf16=True), vsteps, 2)
+        keep("fused_bf16_dc_bf16")
         variants["fused_bf16_dc_bf16"] = {"ms_per_step": round(t_bg * 1e3, 4), "gflops": round(flops / t_bg / 1e9, 1),
                                           "kernel_ms": {k: round(v, 4) for k, v in kt_bg.items()},
                                           "note": "dC rounded to bfloat16 in the step (in the bwd_row time)"}
@@ -1034,6 +1144,9 @@ def main():
         "variants": variants,
     }
     if not args.no_cpu_baseline:
+        # the oracle leg: the CPU baseline, and the oracle as the checker of every variant
+        log("error report against the FP64 oracle (sampled lines)")
+        out["errors"] = error_report(w, outputs, rows_s, cols_s)
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

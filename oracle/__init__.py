@@ -31,27 +31,56 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fmm_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+# Two builds of the same source.  "default" is the one every parity check uses.  "native"
+# adds -O3 and the host's own instruction set, for timing the oracle on the host's cores.
+# Both keep FMA contraction off and never reassociate (no -ffast-math), so every product
+# and sum is rounded once, as written, and the two builds give bit-identical results.
+_BUILDS = {
+    "default": ("liboracle.so", ["-O2"]),
+    "native": ("liboracle_native.so", ["-O3", "-march=native"]),
+}
+_LIB_PATH = os.path.join(_HERE, _BUILDS["default"][0])
+_libs = {}
+_which = "default"
 _lock = threading.Lock()
 
 
-def build(force: bool = False) -> str:
-    """Compile fmm_oracle.c into liboracle.so with gcc (no FMA contraction)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile fmm_oracle.c with gcc (no FMA contraction): liboracle.so, or with
+    ``native`` liboracle_native.so (-O3 -march=native, for timing on this host)."""
+    name, opt = _BUILDS["native" if native else "default"]
+    path = os.path.join(_HERE, name)
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *opt, "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
                                "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
+
+
+def select_build(which: str) -> None:
+    """Route every later oracle call to the "default" or the "native" build.  The native
+    build is compiled here, on first use, for this host's CPU."""
+    global _which
+    if which not in _BUILDS:
+        raise ValueError(which)
+    if which == "native":
+        build(force="native" not in _libs, native=True)
+    with _lock:
+        _which = which
+
+
+def build_flags(which: str = None) -> str:
+    """The gcc optimisation flags of a build (for reports)."""
+    return " ".join(_BUILDS[which or _which][1] + ["-ffp-contract=off", "-fopenmp"])
 
 
 def _load():
-    global _lib
     with _lock:
-        if _lib is None:
-            build()
-            lib = ctypes.CDLL(_LIB_PATH)
+        lib = _libs.get(_which)
+        if lib is None:
+            path = build(native=_which == "native")
+            lib = ctypes.CDLL(path)
             i64, p = ctypes.c_int64, ctypes.c_void_p
             lib.oracle_sddmm.argtypes = [i64, i64, p, p, p, p, p, p, p, i64]
             lib.oracle_spmm_a.argtypes = [i64, i64, p, p, p, p, p, p, i64]
@@ -66,8 +95,8 @@ def _load():
             lib.oracle_gat_edges.restype = None
             for f in ("oracle_sddmm", "oracle_spmm_a", "oracle_spmm_b", "oracle_csr_to_csc"):
                 getattr(lib, f).restype = None
-            _lib = lib
-    return _lib
+            _libs[_which] = lib
+    return lib
 
 
 def _ptr(a):
@@ -290,6 +319,61 @@ def fusedmm_b_backward_sampled(S, ST, A, B, dC, rows, cols):
     dPT = sddmm(ST, dC, A, rows=cols)
     dB = spmm_a(ST, dPT, A, rows=cols)
     return dA, dB
+
+
+class _Rows:
+    """Rows of an array, passed through an elementwise map when taken."""
+
+    def __init__(self, X, f):
+        self.X, self.f = X, f
+
+    def __getitem__(self, idx):
+        x = self.X[idx]
+        return x if self.f is None else self.f(x)
+
+
+def restrict_rows(S, rows):
+    """The stored entries of rows ``rows`` of S as a pattern of their own: row t of the
+    result is row rows[t] of S, and the columns those rows touch are renumbered 0..k-1 in
+    ascending order (so each row stays canonical).  Returns (pattern, cols) with cols[c]
+    the original index of new column c.  Index bookkeeping only: with A[rows] and B[cols],
+    every row of a row-form output (FusedMMA, SDDMM, SpMMA, the adjoint's dA) is the same
+    sum over the same terms in the same order as on S, since rows are independent."""
+    rows = np.asarray(rows, dtype=np.int64)
+    rp = np.asarray(S.rowptr, dtype=np.int64)
+    lens = rp[rows + 1] - rp[rows]
+    ends = np.cumsum(lens)
+    pos = np.repeat(rp[rows] - ends + lens, lens) + np.arange(int(ends[-1]) if rows.size else 0)
+    col = np.asarray(S.colidx, dtype=np.int64)[pos]
+    cols, newcol = np.unique(col, return_inverse=True)
+    sub = SimpleNamespace(m=int(rows.size), n=int(cols.size),
+                          rowptr=np.concatenate([[0], np.cumsum(lens)]).astype(np.int32),
+                          colidx=newcol.astype(np.int32).reshape(-1), val=np.asarray(S.val)[pos])
+    return sub, cols
+
+
+def fusedmm_a_outputs_sampled(S, ST, A, B, dC, rows, cols, prep=None):
+    """Rows ``rows`` of C = FusedMMA(S, A, B) and of its adjoint's dA, and rows ``cols`` of
+    the adjoint's dB, without touching (or converting) any other row of A, B or dC: each is
+    computed on the sub-pattern that holds exactly the entries it sums (rows of S for C and
+    dA, rows of ST = S^T for dB; see restrict_rows).  The arithmetic is that of
+    fusedmm_a and fusedmm_a_backward_sampled.  ``prep`` = (fA, fB, fdC), elementwise maps
+    applied to the rows taken from A, B and dC before use (e.g. bf16_round, np.abs).
+    Returns (C_rows, dA_rows, dB_cols)."""
+    rows, cols = np.asarray(rows, np.int64), np.asarray(cols, np.int64)
+    fA, fB, fG = prep if prep is not None else (None, None, None)
+    A = _Rows(A, fA)
+    B = _Rows(B, fB)
+    dC = _Rows(dC, fG)
+    none = np.zeros(0, np.int64)
+    Sr, cr = restrict_rows(S, rows)            # row t of Sr is row rows[t] of S
+    Ar, Br, Gr = A[rows], B[cr], dC[rows]
+    C = fusedmm_a(Sr, Ar, Br)
+    dA, _ = fusedmm_a_backward_sampled(Sr, transpose(Sr), Ar, Br, Gr, np.arange(Sr.m), none)
+    Tc, rc = restrict_rows(ST, cols)          # column cols[t] of S as row t of Tc, its rows renumbered
+    Sc = transpose(Tc)                         # S restricted to rows rc and columns cols
+    _, dB = fusedmm_a_backward_sampled(Sc, Tc, A[rc], B[cols], dC[rc], none, np.arange(Tc.m))
+    return C, dA, dB
 
 
 # ----------------------------------------------------------------------------------

@@ -1123,23 +1123,29 @@ class BatchPlan:
             flags |= C.FMM_BATCH_DC_BF16
         elif dc_dtype != torch.float32:
             raise TypeError("dC must be float32" + (" or bfloat16" if dcode == C.FMM_BF16 else ""))
+        # every graph is checked before anything is allocated or any library call is made
+        for g, P in enumerate(patterns):
+            if P.device != dev:
+                raise ValueError(f"graph {g}'s pattern is on {P.device}, graph 0's on {dev}")
+            _check_dense("A", A[g], P.m, r, dev)
+            _check_dense("B", B[g], P.n, r, dev)
+            if A[g].dtype != A[0].dtype or B[g].dtype != A[0].dtype:
+                raise TypeError("all graphs need the same storage dtype")
+            _common(P, A[g], B[g])  # the kernel reads stored values as float32
+            if backward:
+                _check_dense("dC", dC[g], P.m, r, dev)
+                if dC[g].dtype != dc_dtype:
+                    raise TypeError("every graph's dC needs the same dtype")
         self.C = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if forward else None
         self.dA = [torch.empty(P.m, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
         self.dB = [torch.empty(P.n, r, dtype=torch.float32, device=dev) for P in patterns] if backward else None
         arr = (C.fmm_batch_graph * len(patterns))()
         for g, P in enumerate(patterns):
-            _check_dense("A", A[g], P.m, r, dev)
-            _check_dense("B", B[g], P.n, r, dev)
-            if A[g].dtype != A[0].dtype or B[g].dtype != A[0].dtype:
-                raise TypeError("all graphs need the same storage dtype")
             x = arr[g]
             x.csr = P.descriptor(C.FMM_CSR, schedule=False)
             x.csc = P.descriptor(C.FMM_CSC, schedule=False)
             x.A, x.B = A[g].data_ptr(), B[g].data_ptr()
             if backward:
-                _check_dense("dC", dC[g], P.m, r, dev)
-                if dC[g].dtype != dc_dtype:
-                    raise TypeError("every graph's dC needs the same dtype")
                 x.dC, x.dA, x.dB = dC[g].data_ptr(), self.dA[g].data_ptr(), self.dB[g].data_ptr()
             if forward:
                 x.C = self.C[g].data_ptr()

@@ -118,3 +118,49 @@ def test_counter_table_aggregates_the_step(tmp_path):
     assert f"{2 * per_launch:.1f} (sum)" in f32
     rounding = (100.0 * 2 + 50.0) * 1024 / 1e6
     assert f"{2 * per_launch + rounding:.1f} (sum)" in dc16
+
+
+def _small_workload():
+    from workloads import dense_normal, rmat
+
+    S = rmat(9, 8, seed=81)
+    r = 8
+    return {"S": S, "r": r, "A": dense_normal(S.m, r, 82), "B": dense_normal(S.n, r, 83),
+            "G": dense_normal(S.m, r, 84)}
+
+
+def test_error_report_measures_each_variant():
+    """The oracle leg's error report: exact outputs give zero error, a planted error in one
+    element of dB is found in dB alone, and bf16 variants are compared both ways."""
+    import numpy as np
+
+    import oracle
+
+    w = _small_workload()
+    S = w["S"]
+    ST = oracle.transpose(S)
+    colptr = np.concatenate([[0], np.cumsum(np.bincount(S.colidx, minlength=S.n))])
+    assert np.array_equal(colptr, ST.rowptr)
+    rows, cols = bench.sample_lines(S.rowptr, 64, 1), bench.sample_lines(colptr, 64, 2)
+    exact = oracle.fusedmm_a_outputs_sampled(S, ST, w["A"], w["B"], w["G"], rows, cols)
+    bad = tuple(x.copy() for x in exact)
+    k = int(np.argmax(np.abs(bad[2]).sum(axis=1)))
+    bad[2][k, 0] += 1e-3 * max(1.0, abs(bad[2][k, 0]))
+    rnd = oracle.bf16_round
+    bf = oracle.fusedmm_a_outputs_sampled(S, ST, w["A"], w["B"], w["G"], rows, cols, prep=(rnd, rnd, None))
+    rep = bench.error_report(w, {"fused_f32": exact, "unfused_f32": bad, "fused_bf16": bf}, rows, cols)
+    assert all(rep["fused_f32"][o]["componentwise"] == 0.0 for o in ("C", "dA", "dB"))
+    assert rep["fused_f32"]["within_gate"]
+    assert rep["unfused_f32"]["C"]["componentwise"] == 0.0 and rep["unfused_f32"]["dA"]["componentwise"] == 0.0
+    assert rep["unfused_f32"]["dB"]["componentwise"] > 1e-5 and not rep["unfused_f32"]["within_gate"]
+    b = rep["fused_bf16"]
+    assert all(b["vs_bf16_rounded_inputs"][o]["componentwise"] == 0.0 for o in ("C", "dA", "dB"))
+    assert 0.0 < b["vs_f32_inputs"]["C"]["componentwise"] <= 2e-2 and b["within_gate"]
+
+
+def test_cpu_baseline_reports_its_sample():
+    w = _small_workload()
+    cb = bench.cpu_baseline(w, target_s=0.05, single_s=0.02)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
+    assert "median of 3 runs" in cb["sample"] and "-march=native" in cb["build"]
+    assert cb["single_thread"]["cores"] == 1 and cb["cpu_model"]

@@ -342,3 +342,27 @@ def test_raw_wrappers_refuse_bad_buffers_before_calling():
     for k, (call, exc) in enumerate(cases):
         with pytest.raises(exc):
             call()
+
+
+def test_batch_plan_refuses_mismatched_graphs_before_calling():
+    """BatchPlan checks every graph before the plan is created: a pattern whose stored
+    values are float64 (the batch kernel reads float32 values) and a pattern on another
+    device than graph 0's are refused with no library call (stand-in patterns, which
+    have no descriptor)."""
+    import torch
+
+    class _Pattern:
+        m, n, nnz, device = 6, 5, 9, torch.device("cpu")
+        val, val_dtype = torch.zeros(9), torch.float32
+
+    class _Float64Pattern(_Pattern):
+        val, val_dtype = torch.zeros(9, dtype=torch.float64), torch.float64
+
+    class _OtherDevicePattern(_Pattern):
+        device = torch.device("meta")
+
+    A, B, G = torch.zeros(6, 8), torch.zeros(5, 8), torch.zeros(6, 8)
+    with pytest.raises(TypeError):
+        F.BatchPlan([_Pattern(), _Float64Pattern()], [A, A], [B, B], [G, G])
+    with pytest.raises(ValueError):
+        F.BatchPlan([_Pattern(), _OtherDevicePattern()], [A, A], [B, B], [G, G])

@@ -17,6 +17,16 @@ from tests.gates import TOL_BF16, TOL_F32
 from tests.gpu_helpers import dev, gate, host, log
 from workloads import workload
 
+# Configurations the benchmark's autotuner chose for R-MAT scale 22, r = 256 on MI355X
+# (batch depth class, split threshold, line order per orientation), for float32 and for
+# bfloat16 storage.  The adjoint test runs under these and under the autotuner's own pick.
+RMAT22_BENCH_TUNING = {
+    "f32": {"csr": {"variant": 3, "long_len": 256, "line_order": False},
+            "csc": {"variant": 3, "long_len": 256, "line_order": False}},
+    "bf16": {"csr": {"variant": 3, "long_len": 256, "line_order": True},
+             "csc": {"variant": 3, "long_len": 256, "line_order": False}},
+}
+
 pytestmark = pytest.mark.gpu
 
 
@@ -149,3 +159,57 @@ def test_rmat20_r64_adjoint_sampled():
     gA, gB = F.fusedmm_b_backward_raw(P, Ad, Bd, Gd)
     gate("rmat20 B dA", host(gA[torch.from_numpy(rows).cuda()]), eA, mA, TOL_F32)
     gate("rmat20 B dB", host(gB[torch.from_numpy(cols).cuda()]), eB, mB, TOL_F32)
+
+
+@pytest.mark.timeout(1200)
+def test_rmat22_r256_adjoint_sampled():
+    """The adjoint at the bench's own workload: dA on sampled rows and dB on sampled columns
+    (random ones, the 16 longest, which the split schedule cuts into chunks, and empty
+    ones), with float32 storage, bfloat16 storage, and bfloat16 storage with a bfloat16
+    upstream gradient, under the bench's tuning and the autotuner's pick."""
+    w = workload("rmat22_ef16_r256")
+    S = w["S"]
+    log(f"rmat22 adjoint: nnz={S.nnz} building pattern")
+    P = F.Pattern.from_csr(S)
+    ST = oracle.transpose(S)
+    rows = _sample_lines(S.rowptr, 1024, 21)
+    cols = _sample_lines(ST.rowptr, 1024, 22)
+    lens_c = np.diff(ST.rowptr.astype(np.int64))
+    assert lens_c[cols].max() == lens_c.max() > 50000 and (lens_c[cols] == 0).any()
+    A, B, G = w["A"], w["B"], w["G"]
+    rnd, ab = oracle.bf16_round, np.abs
+    rab = lambda x: np.abs(oracle.bf16_round(x))  # noqa: E731
+    SA, STA = oracle.absolute(S), oracle.absolute(ST)
+
+    def refs(prep, prep_mag):
+        return (oracle.fusedmm_a_outputs_sampled(S, ST, A, B, G, rows, cols, prep=prep),
+                oracle.fusedmm_a_outputs_sampled(SA, STA, A, B, G, rows, cols, prep=prep_mag))
+
+    log("rmat22 adjoint: oracle references")
+    ref32 = refs(None, (ab, ab, ab))
+    ri, ci = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    Ad32, Bd32, Gd = dev(A), dev(B), dev(G)
+    Ad16, Bd16 = F.to_bf16(Ad32), F.to_bf16(Bd32)
+    Gd16 = F.to_bf16(Gd)
+    cases = (("f32", Ad32, Bd32, Gd, TOL_F32, None),
+             ("bf16", Ad16, Bd16, Gd, TOL_BF16, ((rnd, rnd, None), (rab, rab, ab))),
+             ("bf16_dc_bf16", Ad16, Bd16, Gd16, TOL_BF16, ((rnd, rnd, rnd), (rab, rab, rab))))
+    for tag, Ad, Bd, Gi, tol, rounded in cases:
+        refq = refs(*rounded) if rounded else None
+        for how in ("bench tuning", "autotuned"):
+            if how == "bench tuning":
+                P.apply_tuning(RMAT22_BENCH_TUNING["f32" if tag == "f32" else "bf16"])
+            else:
+                log(f"rmat22 adjoint {tag}: autotune")
+                P.autotune(Ad, Bd, Gd, form="a")
+            log(f"rmat22 adjoint {tag} {how}: {P.tuning}")
+            Cg, _ = F.fusedmm_a_raw(P, Ad, Bd)
+            gA, gB = F.fusedmm_a_backward_raw(P, Ad, Bd, Gi)
+            got = (host(Cg[ri]), host(gA[ri]), host(gB[ci]))
+            del Cg, gA, gB
+            for name, x, e, mg in zip(("C", "dA", "dB"), got, ref32[0], ref32[1]):
+                gate(f"rmat22 {tag} {how} {name}", x, e, mg, tol)
+            if refq is not None:
+                for name, x, e, mg in zip(("C", "dA", "dB"), got, refq[0], refq[1]):
+                    gate(f"rmat22 {tag} {how} {name} (rounded inputs)", x, e, mg, TOL_F32)
+            torch.cuda.empty_cache()

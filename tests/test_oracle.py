@@ -354,6 +354,43 @@ def test_sampled_forms_match_full():
     assert np.array_equal(oracle.fusedmm_a_rows(S, A, B, rows), oracle.fusedmm_a(S, A, B)[rows])
 
 
+def test_restricted_samples_match_full():
+    # the sampled outputs computed on restricted patterns equal the full computation bit for
+    # bit (same terms, same order), for float32 inputs, with empty and repeated lines
+    S = rmat(10, 8, seed=71)
+    ST = oracle.transpose(S)
+    r = 16
+    A, B, G = dense_normal(S.m, r, 72), dense_normal(S.n, r, 73), dense_normal(S.m, r, 74)
+    lens_r, lens_c = np.diff(S.rowptr), np.diff(ST.rowptr)
+    rows = np.array([int(np.argmax(lens_r)), int(np.flatnonzero(lens_r == 0)[0]), 0, 1023, 5, 5])
+    cols = np.array([int(np.argmax(lens_c)), int(np.flatnonzero(lens_c == 0)[0]), 3, 1023, 3])
+    C, dA, dB = oracle.fusedmm_a_outputs_sampled(S, ST, A, B, G, rows, cols)
+    fA, fB = oracle.fusedmm_a_backward(S, A, B, G)
+    assert np.array_equal(C, oracle.fusedmm_a(S, A, B)[rows])
+    assert np.array_equal(dA, fA[rows])
+    assert np.array_equal(dB, fB[cols])
+    sub, cmap = oracle.restrict_rows(S, rows)
+    assert sub.m == rows.size and np.all(np.diff(cmap) > 0)
+    for t, i in enumerate(rows):
+        got = cmap[sub.colidx[sub.rowptr[t]:sub.rowptr[t + 1]]]
+        assert np.array_equal(got, S.colidx[S.rowptr[i]:S.rowptr[i + 1]])
+
+
+def test_native_build_is_bit_identical():
+    # the -O3 -march=native build (timed on the host) computes exactly what the parity
+    # build computes: contraction stays off and nothing is reassociated
+    case = tiny_case(40, 30, 24, 0.3, seed=75)
+    S, A, B, G = case["S"], case["A"], case["B"], case["G"]
+    ref = (oracle.fusedmm_a(S, A, B),) + oracle.fusedmm_a_backward(S, A, B, G) + oracle.csr_to_csc(S)
+    try:
+        oracle.select_build("native")
+        got = (oracle.fusedmm_a(S, A, B),) + oracle.fusedmm_a_backward(S, A, B, G) + oracle.csr_to_csc(S)
+    finally:
+        oracle.select_build("default")
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+
+
 def test_bf16_round_matches_torch():
     rng = np.random.default_rng(70)
     x = np.concatenate([
