@@ -58,6 +58,13 @@ def kernel_bytes_min(kind, m, n, nnz, r, e):
     raise ValueError(kind)
 
 
+def batch_graph_bytes_min(m, n, nnz, r, e, ed):
+    """Compulsory bytes of one graph's fused forward + adjoint in the batched launch: the CSR
+    and CSC index arrays and values, A and B (e bytes per element), dC (ed), and the outputs
+    C, dA, dB (float32), each once."""
+    return 4 * (m + 1) + 8 * nnz + 4 * (n + 1) + 8 * nnz + e * (m + n) * r + ed * m * r + 4 * (2 * m + n) * r
+
+
 def gat_forward_bytes(n, nnz, r, e):
     """Gather-model bytes of one attention head's forward: the scores pass reads H once and
     writes s, t; the line pass reads rowptr, colidx + value and t_j per entry, gathers H_j
@@ -462,7 +469,7 @@ def run_batch(args):
     plan = F.BatchPlan(pats, A, B, G)
     if args.tuned:  # TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE, as a bench run's autotune chose it
         tile, xcd, roww, colw = (int(x) for x in args.tuned.split(":"))
-        plan.set_schedule(tile, bool(xcd), bool(roww), bool(colw))
+        plan.set_schedule(tile, xcd, bool(roww), bool(colw))
         info = plan.info()
         log(f"schedule from --tuned: {info}")
     else:
@@ -489,16 +496,19 @@ def run_batch(args):
     log(f"batched fwd+bwd {t_step * 1e3:.3f} ms ({k_ms:.3f} ms by events) -> {gflops:.1f} GFLOP/s")
 
     e = 2
-    bytes_launch = 0
+    bytes_launch = 0   # gather model, summed over the three passes of every graph
+    bytes_min = 0      # compulsory: every array of every graph once per launch
     for g in graphs:
         S = g["S"]
         for kind in ("fwd", "bwd_row", "bwd_col"):
             bytes_launch += kernel_bytes(kind, S.m, S.n, S.nnz, r, e)
-    achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+        bytes_min += batch_graph_bytes_min(S.m, S.n, S.nnz, r, e, 4)
+    achieved = bytes_min / (k_ms * 1e-3) / 1e9
     # counter-measured bytes per launch of the chosen schedule's kernel, when the committed
     # counter summary covers the current sources
     waves = 64 // info["lanes"]  # line groups sharing a wavefront in the wavefront-per-line schedule
-    kernel_key = (f"void fmm::batch_kernel<unsigned short, float, {info['lanes']}, 8, "
+    kname = "batch_queue_kernel" if info["xcd_aware"] == 2 else "batch_kernel"
+    kernel_key = (f"void fmm::{kname}<unsigned short, float, {info['lanes']}, 8, "
                   f"{waves if info['row_schedule'] else 1}, {waves if info['col_schedule'] else 1}>")
     traffic = None
     f = os.path.join(ROOT, "profiles", "traffic_batch256_r64.json")
@@ -567,11 +577,15 @@ def run_batch(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else int(traffic),
                      "traffic_gbs": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9, 1),
-                     "traffic_frac": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "kernel": f"batch_kernel (persistent, all passes): {kernel_key}", "kernel_ms": round(k_ms, 4),
-                     "bytes_per_launch": int(bytes_launch),
-                     "bytes_model": "gather (each stored entry fetches its dense rows); rows that hit in L2 make "
-                                    "the counter traffic smaller"},
+                     "frac_counters": None if traffic is None else
+                     round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic_over_compulsory": None if traffic is None else round(traffic / bytes_min, 3),
+                     "kernel": f"{kname} (persistent, all passes): {kernel_key}", "kernel_ms": round(k_ms, 4),
+                     "bytes_per_launch": int(bytes_min),
+                     "bytes_model": "compulsory: every array of every graph once per launch (rows gathered "
+                                    "again hit in L2, so the gather model is no bound here)",
+                     "bytes_gather_model": int(bytes_launch),
+                     "frac_gather_model": round(bytes_launch / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "variants": variants,
     }
     if args.calibrate_copy:
@@ -777,6 +791,65 @@ def copy_ceiling(dev, reps=10):
             "kernels": "fmm_stream_copy (read + write), fmm_stream_read (read only), torch copy_"}
 
 
+GATHER_ROW_BYTES = (128, 256, 512, 1024)
+
+
+def calibrate_gather(dev, reps=3):
+    """Gather probes of known size for counter calibration: each row of a PROBE_BYTES buffer
+    read once, in a seeded random order, at each of GATHER_ROW_BYTES per row (the row sizes
+    of the workloads' gathered rows: 64 bf16 or 32 fp32 elements up to 256 fp32), `reps`
+    times each; then the plain copies of --calibrate-copy."""
+    import torch
+
+    import paper_2203_07673_amd as F
+
+    src = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    for rb in GATHER_ROW_BYTES:
+        rows = torch.randperm(PROBE_BYTES // rb, generator=gen, device=dev, dtype=torch.int32)
+        for _ in range(reps):
+            F.stream_gather(src, rb, rows, sink)
+        torch.cuda.synchronize()
+        del rows
+    calibrate_copy(dev)
+
+
+def gather_summary(fetch_dir, out_md, command=""):
+    """FETCH_SIZE of the gather probes against the bytes they move (every row once plus its
+    4-byte index), next to the plain copy's scale: the factor each access shape needs."""
+    per = {}
+    for row in _csv_rows(fetch_dir, "counter_collection.csv"):
+        if row.get("Counter_Name") == "FETCH_SIZE":
+            per[int(row["Dispatch_Id"])] = (row["Kernel_Name"], float(row["Counter_Value"]))
+    lines = ["# FETCH_SIZE scale on gather-shaped traffic", "", f"Command: `{command}`", "",
+             f"Each probe reads every row of a {PROBE_BYTES >> 30} GiB buffer once, in a seeded random order "
+             "(default cache policy, one 16-byte load per lane, as the line kernels gather rows). Known bytes = "
+             "rows x (row bytes + 4 index bytes). Scale = known bytes / (FETCH_SIZE KiB x 1024).", "",
+             "| probe | dispatches | FETCH_SIZE (KiB, mean) | known bytes | scale |", "|---|---|---|---|---|"]
+    out = {}
+    for rb in GATHER_ROW_BYTES:
+        tag = f"gather_rows_kernel<{rb // 16}>"
+        vals = [v for k, v in per.values() if tag in k.replace(" ", "")]
+        if not vals:
+            continue
+        n = PROBE_BYTES // rb
+        known = n * (rb + 4)
+        kib = sum(vals) / len(vals)
+        out[rb] = known / (kib * 1024.0)
+        lines.append(f"| gather, {rb} B rows | {len(vals)} | {kib:.0f} | {known} | {out[rb]:.3f} |")
+    calib = calibration_dispatches(per)
+    if calib:
+        kib = sum(per[i][1] for i in calib) / len(calib)
+        lines.append(f"| plain device copy of {COPY_BYTES >> 30} GiB (reads) | {len(calib)} | {kib:.0f} | "
+                     f"{COPY_BYTES} | {COPY_BYTES / (kib * 1024.0):.3f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return out
+
+
 def cold_cache_steps(step, reps, kinds, dev):
     """The step timed with L2 and MALL flushed before each repetition (a 1 GiB scratch
     buffer is overwritten between steps, outside the timed events)."""
@@ -848,6 +921,10 @@ def main():
                     help="csr=VARIANT:LONG_LEN:ORDER,csc=VARIANT:LONG_LEN:ORDER as a bench run's autotune chose "
                          "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1); for batch256_r64 "
                          "TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE")
+    ap.add_argument("--calibrate-gather", action="store_true",
+                    help="run only the gather probes of known size and the plain copies (for a --pmc run)")
+    ap.add_argument("--gather-summary", nargs=2, metavar=("FETCH_DIR", "OUT_MD"),
+                    help="summarise a FETCH_SIZE run of --calibrate-gather and exit")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -859,11 +936,20 @@ def main():
     if args.counter_table:
         counter_table(args.counter_table[0], args.counter_table[1:], command=args.command)
         return
+    if args.gather_summary:
+        gather_summary(*args.gather_summary, command=args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_gather:
+        import torch
+
+        torch.cuda.set_device(0)
+        calibrate_gather(torch.device("cuda:0"))
+        return
     if args.workload == "batch256_r64":
         run_batch(args)
         return

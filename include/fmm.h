@@ -153,6 +153,17 @@ fmm_status fmm_device_info(int32_t *num_cu, char *arch, int32_t arch_len);
  */
 fmm_status fmm_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
 fmm_status fmm_stream_read(const void *src, size_t bytes, uint32_t key, uint32_t *sink, hipStream_t stream);
+/*
+ * Gather probe (measurement only): reads rows rows[0 .. n_rows-1] of src, each row_bytes
+ * long (16 * 2^k bytes, k = 0..6, else FMM_ERR_DIM), one lane per 16 bytes with the
+ * default cache policy, the way the line kernels gather rows; folds them into *sink as
+ * fmm_stream_read does.  With rows a permutation of the rows of a buffer larger than the
+ * caches, every row comes from memory once, so the pass moves a known number of bytes
+ * (n_rows * row_bytes, plus 4 * n_rows of indices), to calibrate hardware counters on
+ * gather-shaped traffic.  The caller keeps every rows[k] inside src.
+ */
+fmm_status fmm_stream_gather(const void *src, size_t row_bytes, const int32_t *rows, int64_t n_rows, uint32_t key,
+                             uint32_t *sink, hipStream_t stream);
 
 /*
  * Lane-group shape override for every later launch in this process (tuning and
@@ -178,6 +189,10 @@ fmm_status fmm_launch_shape(const fmm_sparse *S, int32_t two_row, int32_t r, int
 /*
  * Check that S is canonical (see conventions): ptr[0] == 0, ptr[major] == nnz, ptr
  * non-decreasing, 0 <= idx < minor extent, idx strictly increasing in each line.
+ * The paper keeps its sparse blocks as coordinate lists and says nothing of order or
+ * repeated coordinates (Section V); this library reads S as the set of its stored
+ * entries, one per coordinate, so the CSR of S and its stored transposed copy (Section
+ * IV-B) are unique, and the hot calls rely on that form.
  * Synchronous.  Returns FMM_OK, FMM_ERR_INDEX or FMM_ERR_NONCANONICAL.  Allocates
  * a 4-byte device flag for the duration of the call.
  */
@@ -326,6 +341,11 @@ fmm_status fmm_autotune(int32_t op, fmm_sparse *S_csr, fmm_sparse *S_csc, const 
 /* ---------------------------------------------------------------- backward */
 
 /*
+ * The paper gives no adjoints.  Every call below is the chain rule through the forward
+ * definitions it names (Section II; the sampled product per entry, Eq. (1) and Section
+ * IV-A), with S's stored values held fixed unless the call says otherwise.  They match
+ * central finite differences and dense autograd in the oracle's tests.
+ *
  * Adjoint of C = FusedMMA(S, A, B) for fixed S, with upstream gradient dC (rows x r):
  *   dP = S * (dC B^T)          (the gradient reaching A B^T, an SDDMM)
  *   dA = dP B                  = FusedMMA(S, dC, B)            (row pass on S_csr)
@@ -344,7 +364,8 @@ fmm_status fmm_fusedmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_c
                                   void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Adjoint of C' = FusedMMB(S, A, B) with upstream gradient dC (cols x r):
+ * Adjoint of C' = FusedMMB(S, A, B) (Section II; FusedMMA on the transposed copy,
+ * Section IV-B) with upstream gradient dC (cols x r):
  *   dP = S * (A dC^T)
  *   dA = dP B + R dC           (row pass on S_csr)
  *   dB = dP^T A                = FusedMMB(S, A, dC)            (column pass on S_csc)
@@ -385,7 +406,7 @@ fmm_status fmm_fusedmm_b_backward_values(const fmm_sparse *S_csr, const fmm_spar
                                          void *dB, int32_t flags, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Adjoint of R = SDDMM(A, B, S) with upstream gradient dR (nnz, CSR order):
+ * Adjoint of R = SDDMM(A, B, S) (Eq. (1)) with upstream gradient dR (nnz, CSR order):
  *   dA = (S * dR) B on S_csr,  dB = (S * dR)^T A on S_csc (reads dR through perm).
  */
 fmm_status fmm_sddmm_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, const void *A,
@@ -393,7 +414,7 @@ fmm_status fmm_sddmm_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc, 
                               void *dB, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Adjoint of C = SpMMA with stored values w (CSR order; NULL = S's values):
+ * Adjoint of C = SpMMA(W, B) (Section II) with stored values w (CSR order; NULL = S's values):
  *   dw[p] = <dC_i:, B_j:>        (nnz, CSR order; the gradient of the stored values)
  *   dB    = W^T dC               on S_csc (reads w through perm)
  */
@@ -402,7 +423,8 @@ fmm_status fmm_spmm_a_backward(const fmm_sparse *S_csr, const fmm_sparse *S_csc,
                                void *dB, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Adjoint of C' = SpMMB with stored values w (CSR order; NULL = S's values), dC': cols x r:
+ * Adjoint of C' = SpMMB(W, A) (Section II) with stored values w (CSR order; NULL = S's
+ * values), dC': cols x r:
  *   dw[p] = <A_i:, dC'_j:>       (nnz, CSR order)
  *   dA    = W dC'                on S_csr
  */
@@ -526,16 +548,30 @@ fmm_status fmm_sddmm_residual(const fmm_sparse *S_csr, const void *A, const void
  *   - row-block: L lanes per line, several lines per wave;
  *   - wavefront-per-line: the 64 lanes of a wave share one line, each lane group
  *     taking every (64/L)-th batch of entries, partial sums added across groups;
- *   - XCD-aware placement: all tiles of a graph go to workgroups of one XCD (workgroup
- *     ids are dealt round-robin over the 8 XCDs of gfx950), so a graph's gathered rows
- *     stay in that XCD's L2.
+ * Placements of the tiles on the grid (workgroup ids are dealt round-robin over the 8
+ * XCDs of gfx950, each with its own L2):
+ *   - FMM_BATCH_PLACE_GLOBAL: every tile to the least-loaded workgroup (LPT), fixed lists;
+ *   - FMM_BATCH_PLACE_XCD: graphs go to XCDs by LPT and each graph's tiles to that XCD's
+ *     workgroups, fixed lists;
+ *   - FMM_BATCH_PLACE_QUEUES: graphs go to XCDs by LPT, and the workgroups of an XCD claim
+ *     its tiles one at a time, in order, from a queue (a device counter), so the XCD
+ *     works through one graph at a time while the graph's gathered rows sit in its L2
+ *     (the cache blocking of Section III-A, at the level of the XCD's L2); a workgroup
+ *     whose queue is drained claims from the next ones.  The forward and dA tiles of a
+ *     line range are queued side by side, since both gather the same rows of B.  The
+ *     last workgroup of a launch puts the counters back to zero, so launches of one plan
+ *     (eager or replayed) must not overlap in time.
  * fmm_batch_autotune times candidate schedules with HIP events and keeps the fastest.
- * Results are deterministic for a fixed schedule; with the row-block schedule they equal
- * the single-graph calls bit for bit.
+ * Results are deterministic for a fixed schedule (each line is computed by one tile, in a
+ * fixed order, whichever workgroup claims it); with the row-block schedule they equal the
+ * single-graph calls bit for bit under every placement.
  */
 #define FMM_BATCH_FWD 1   /* compute C_g = FusedMMA(S_g, A_g, B_g)                        */
 #define FMM_BATCH_BWD 2   /* compute dA_g, dB_g for upstream gradient dC_g                */
 #define FMM_BATCH_DC_BF16 4 /* with FMM_BATCH_BWD and FMM_BF16: every dC_g is bfloat16     */
+#define FMM_BATCH_PLACE_GLOBAL 0 /* placements (fmm_batch_set_schedule's xcd_aware)        */
+#define FMM_BATCH_PLACE_XCD 1
+#define FMM_BATCH_PLACE_QUEUES 2
 
 typedef struct fmm_batch_graph {
     fmm_sparse csr;       /* rows x cols CSR descriptor of S_g (its split schedule is ignored) */
@@ -553,7 +589,7 @@ typedef struct fmm_batch_plan fmm_batch_plan;
 
 typedef struct fmm_batch_info {
     int32_t tile_nnz;       /* target stored entries per tile                              */
-    int32_t xcd_aware;      /* 1: graphs pinned to XCDs                                     */
+    int32_t xcd_aware;      /* placement: FMM_BATCH_PLACE_GLOBAL, _XCD or _QUEUES           */
     int32_t lanes;          /* L                                                            */
     int32_t row_schedule;   /* 0 row-block, 1 wavefront-per-line (forward and dA passes)    */
     int32_t col_schedule;   /* same, for the dB column pass                                 */
@@ -571,7 +607,8 @@ typedef struct fmm_batch_info {
  * FMM_ERR_UNSUPPORTED) when the upstream gradients are stored as bfloat16.  Synchronous: copies the pointer arrays of every graph to the
  * host to cut nnz-balanced tiles, then allocates and uploads the tables.  The default
  * schedule (before autotuning) is row-block, XCD-aware, tile_nnz 8192.  The graphs'
- * device buffers must stay valid for the life of the plan.
+ * device buffers must stay valid for the life of the plan.  The plan also owns the
+ * queue counters of FMM_BATCH_PLACE_QUEUES (zeroed here).
  */
 fmm_status fmm_batch_plan_create(const fmm_batch_graph *graphs, int32_t nbatch, int32_t r, int32_t dtype,
                                  int32_t flags, fmm_batch_plan **plan);
@@ -586,7 +623,9 @@ fmm_status fmm_batch_capture(fmm_batch_plan *plan, hipStream_t stream);
 /* Replay the captured graph on stream (FMM_ERR_STATE if none is current). */
 fmm_status fmm_batch_launch(fmm_batch_plan *plan, hipStream_t stream);
 fmm_status fmm_batch_plan_info(const fmm_batch_plan *plan, fmm_batch_info *info);
-/* Force a schedule (as fmm_batch_autotune would pick it); invalidates a captured graph. */
+/* Force a schedule (as fmm_batch_autotune would pick it): tile_nnz >= 1, xcd_aware one of
+   FMM_BATCH_PLACE_*, row/col schedule 0 (row-block) or 1 (wavefront-per-line);
+   FMM_ERR_DIM otherwise.  Invalidates a captured graph. */
 fmm_status fmm_batch_set_schedule(fmm_batch_plan *plan, int32_t tile_nnz, int32_t xcd_aware,
                                   int32_t row_schedule, int32_t col_schedule);
 void fmm_batch_plan_destroy(fmm_batch_plan *plan);

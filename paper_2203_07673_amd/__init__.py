@@ -35,6 +35,7 @@ from .fusedmm import (  # noqa: F401
     spmm_b,
     spmm_b_raw,
     stream_copy,
+    stream_gather,
     stream_read,
     to_bf16,
 )

@@ -25,7 +25,8 @@ struct fmm_batch_plan {
     // current schedule
     int32_t tile_nnz = 8192, xcd = 1, rw = 0, cw = 0;
     BatchTile *tiles_dev = nullptr;
-    int32_t *wgoff_dev = nullptr;
+    int32_t *wgoff_dev = nullptr;  // per workgroup (static placement) or per queue (queues) tile offsets
+    int32_t *qnext_dev = nullptr;  // queue counters plus the finished-workgroup count (zero between launches)
     int32_t n_tiles = 0, n_wg = 0;
     // tuning record
     int32_t n_candidates = 0;
@@ -57,6 +58,22 @@ BatchKernelFn kernel_for(const fmm_batch_plan *p, int rw, int cw)
         return batch_kernel_for<bf16_t, float>(p->L, rw, cw);
     }
     return batch_kernel_for<float, float>(p->L, rw, cw);
+}
+
+BatchQueueKernelFn queue_kernel_for(const fmm_batch_plan *p, int rw, int cw)
+{
+    if (p->dtype == FMM_BF16) {
+        if (p->flags & FMM_BATCH_DC_BF16) return batch_queue_kernel_for<bf16_t, bf16_t>(p->L, rw, cw);
+        return batch_queue_kernel_for<bf16_t, float>(p->L, rw, cw);
+    }
+    return batch_queue_kernel_for<float, float>(p->L, rw, cw);
+}
+
+// Kernel of a schedule, for occupancy queries.
+const void *kernel_address(const fmm_batch_plan *p, int32_t placement, int rw, int cw)
+{
+    if (placement == FMM_BATCH_PLACE_QUEUES) return reinterpret_cast<const void *>(queue_kernel_for(p, rw, cw));
+    return reinterpret_cast<const void *>(kernel_for(p, rw, cw));
 }
 
 struct TileCost {
@@ -98,6 +115,26 @@ void cut_tiles(const fmm_batch_plan *p, int32_t tile_nnz, std::vector<std::vecto
     }
 }
 
+// Graphs to XCDs by LPT on graph cost (largest first, each to the least-loaded XCD).
+std::vector<std::vector<int32_t>> graphs_to_xcds(const fmm_batch_plan *p,
+                                                 const std::vector<std::vector<TileCost>> &per_graph, int nx)
+{
+    std::vector<double> gcost(p->nbatch, 0.0);
+    for (int32_t g = 0; g < p->nbatch; ++g)
+        for (const TileCost &t : per_graph[g]) gcost[g] += t.cost;
+    std::vector<int32_t> order(p->nbatch);
+    for (int32_t g = 0; g < p->nbatch; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return gcost[a] > gcost[b]; });
+    std::vector<double> xload(nx, 0.0);
+    std::vector<std::vector<int32_t>> xgraphs(nx);
+    for (int32_t g : order) {
+        const int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+        xload[x] += gcost[g];
+        xgraphs[x].push_back(g);
+    }
+    return xgraphs;
+}
+
 // Place tiles on n_wg workgroups.  XCD-aware: graphs go to XCDs by LPT on graph cost,
 // then each graph's tiles go, in order, to the least-loaded workgroup of its XCD
 // (workgroup w runs on XCD w % n_xcd), so the XCD works through its graphs one after
@@ -109,19 +146,7 @@ void place_tiles(const fmm_batch_plan *p, const std::vector<std::vector<TileCost
     typedef std::pair<double, int32_t> Load;  // (load, workgroup)
     if (xcd && p->n_xcd > 1 && n_wg % p->n_xcd == 0) {
         const int nx = p->n_xcd;
-        std::vector<double> gcost(p->nbatch, 0.0);
-        for (int32_t g = 0; g < p->nbatch; ++g)
-            for (const TileCost &t : per_graph[g]) gcost[g] += t.cost;
-        std::vector<int32_t> order(p->nbatch);
-        for (int32_t g = 0; g < p->nbatch; ++g) order[g] = g;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return gcost[a] > gcost[b]; });
-        std::vector<double> xload(nx, 0.0);
-        std::vector<std::vector<int32_t>> xgraphs(nx);
-        for (int32_t g : order) {
-            const int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
-            xload[x] += gcost[g];
-            xgraphs[x].push_back(g);
-        }
+        const std::vector<std::vector<int32_t>> xgraphs = graphs_to_xcds(p, per_graph, nx);
         for (int x = 0; x < nx; ++x) {
             std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
             for (int32_t w = x; w < n_wg; w += nx) heap.push(Load(0.0, w));
@@ -158,6 +183,31 @@ void place_tiles(const fmm_batch_plan *p, const std::vector<std::vector<TileCost
     (*wgoff)[n_wg] = (int32_t)tiles->size();
 }
 
+// Queues: one per XCD, holding its graphs (largest first) one after another.  Inside a
+// graph the forward and dA tiles of the same line range sit side by side (both gather
+// the same rows of B), then come the dB tiles.  qoff[q] .. qoff[q + 1] - 1 are queue q's.
+void queue_tiles(const fmm_batch_plan *p, const std::vector<std::vector<TileCost>> &per_graph,
+                 std::vector<BatchTile> *tiles, std::vector<int32_t> *qoff)
+{
+    const int nq = p->n_xcd;
+    const std::vector<std::vector<int32_t>> xgraphs = graphs_to_xcds(p, per_graph, nq);
+    tiles->clear();
+    qoff->assign(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) {
+        (*qoff)[q] = (int32_t)tiles->size();
+        for (int32_t g : xgraphs[q]) {
+            std::vector<BatchTile> rowp, colp;
+            for (const TileCost &t : per_graph[g]) (t.t.pass == PASS_BWD_COL ? colp : rowp).push_back(t.t);
+            std::stable_sort(rowp.begin(), rowp.end(), [](const BatchTile &a, const BatchTile &b) {
+                return a.l0 != b.l0 ? a.l0 < b.l0 : a.pass < b.pass;
+            });
+            tiles->insert(tiles->end(), rowp.begin(), rowp.end());
+            tiles->insert(tiles->end(), colp.begin(), colp.end());
+        }
+    }
+    (*qoff)[nq] = (int32_t)tiles->size();
+}
+
 void release_graph(fmm_batch_plan *p)
 {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -169,31 +219,32 @@ void release_graph(fmm_batch_plan *p)
 
 // Build and upload the tables of a schedule; the grid is every CU times the resident
 // workgroups of the schedule's kernel.
-fmm_status apply_schedule(fmm_batch_plan *p, int32_t tile_nnz, int32_t xcd, int32_t rw, int32_t cw)
+fmm_status apply_schedule(fmm_batch_plan *p, int32_t tile_nnz, int32_t placement, int32_t rw, int32_t cw)
 {
-    BatchKernelFn fn = kernel_for(p, rw, cw);
+    const void *fn = kernel_address(p, placement, rw, cw);
     if (!fn) return FMM_ERR_UNSUPPORTED;
     int per_cu = 0;
-    BTRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), kBlock, 0));
+    BTRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
     if (per_cu < 1) per_cu = 1;
     const int32_t n_wg = p->num_cu * per_cu;
     std::vector<std::vector<TileCost>> per_graph;
     cut_tiles(p, tile_nnz, &per_graph);
     std::vector<BatchTile> tiles;
-    std::vector<int32_t> wgoff;
-    place_tiles(p, per_graph, n_wg, xcd != 0, &tiles, &wgoff);
+    std::vector<int32_t> off;
+    if (placement == FMM_BATCH_PLACE_QUEUES) queue_tiles(p, per_graph, &tiles, &off);
+    else place_tiles(p, per_graph, n_wg, placement == FMM_BATCH_PLACE_XCD, &tiles, &off);
     release_graph(p);
     if (p->tiles_dev) BTRY(hipFree(p->tiles_dev));
     if (p->wgoff_dev) BTRY(hipFree(p->wgoff_dev));
     p->tiles_dev = nullptr;
     p->wgoff_dev = nullptr;
     BTRY(hipMalloc(&p->tiles_dev, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile)));
-    BTRY(hipMalloc(&p->wgoff_dev, wgoff.size() * sizeof(int32_t)));
+    BTRY(hipMalloc(&p->wgoff_dev, off.size() * sizeof(int32_t)));
     if (!tiles.empty())
         BTRY(hipMemcpy(p->tiles_dev, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
-    BTRY(hipMemcpy(p->wgoff_dev, wgoff.data(), wgoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    BTRY(hipMemcpy(p->wgoff_dev, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     p->tile_nnz = tile_nnz;
-    p->xcd = xcd;
+    p->xcd = placement;
     p->rw = rw;
     p->cw = cw;
     p->n_tiles = (int32_t)tiles.size();
@@ -203,11 +254,18 @@ fmm_status apply_schedule(fmm_batch_plan *p, int32_t tile_nnz, int32_t xcd, int3
 
 hipError_t launch(fmm_batch_plan *p, hipStream_t s)
 {
-    BatchKernelFn fn = kernel_for(p, p->rw, p->cw);
     const BatchGraphDev *g = p->graphs_dev;
     const BatchTile *t = p->tiles_dev;
     const int32_t *w = p->wgoff_dev;
     int32_t r = p->r;
+    if (p->xcd == FMM_BATCH_PLACE_QUEUES) {
+        BatchQueueKernelFn fn = queue_kernel_for(p, p->rw, p->cw);
+        int32_t *next = p->qnext_dev;
+        int32_t nq = p->n_xcd;
+        void *args[] = {&g, &t, &w, &next, &nq, &r};
+        return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(p->n_wg), dim3(kBlock), args, 0, s);
+    }
+    BatchKernelFn fn = kernel_for(p, p->rw, p->cw);
     void *args[] = {&g, &t, &w, &r};
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(p->n_wg), dim3(kBlock), args, 0, s);
 }
@@ -308,11 +366,14 @@ fmm_status fmm_batch_plan_create(const fmm_batch_graph *graphs, int32_t nbatch, 
     e = hipMalloc(&p->graphs_dev, sizeof(BatchGraphDev) * nbatch);
     if (e == hipSuccess)
         e = hipMemcpy(p->graphs_dev, p->graphs.data(), sizeof(BatchGraphDev) * nbatch, hipMemcpyHostToDevice);
+    // queue counters: zero here, and put back to zero by the last workgroup of every launch
+    if (e == hipSuccess) e = hipMalloc(&p->qnext_dev, sizeof(int32_t) * (p->n_xcd + 1));
+    if (e == hipSuccess) e = hipMemset(p->qnext_dev, 0, sizeof(int32_t) * (p->n_xcd + 1));
     if (e != hipSuccess) {
         fmm_batch_plan_destroy(p);
         return hipfail(e);
     }
-    fmm_status st = apply_schedule(p, 8192, 1, 0, 0);
+    fmm_status st = apply_schedule(p, 8192, FMM_BATCH_PLACE_XCD, 0, 0);
     if (st != FMM_OK) {
         fmm_batch_plan_destroy(p);
         return st;
@@ -325,8 +386,8 @@ fmm_status fmm_batch_set_schedule(fmm_batch_plan *p, int32_t tile_nnz, int32_t x
                                   int32_t col_schedule)
 {
     if (!p) return FMM_ERR_NULL;
-    if (tile_nnz < 1 || xcd_aware < 0 || xcd_aware > 1 || row_schedule < 0 || row_schedule > 1 || col_schedule < 0 ||
-        col_schedule > 1)
+    if (tile_nnz < 1 || xcd_aware < FMM_BATCH_PLACE_GLOBAL || xcd_aware > FMM_BATCH_PLACE_QUEUES ||
+        row_schedule < 0 || row_schedule > 1 || col_schedule < 0 || col_schedule > 1)
         return FMM_ERR_DIM;
     return apply_schedule(p, tile_nnz, xcd_aware, row_schedule, col_schedule);
 }
@@ -353,7 +414,7 @@ fmm_status fmm_batch_autotune(fmm_batch_plan *p, hipStream_t stream)
     int32_t count = 0;
     fmm_status st = FMM_OK;
     for (int ti = 0; ti < 3 && st == FMM_OK; ++ti) {
-        for (int x = 1; x >= 0 && st == FMM_OK; --x) {
+        for (int x = FMM_BATCH_PLACE_QUEUES; x >= FMM_BATCH_PLACE_GLOBAL && st == FMM_OK; --x) {
             for (int rw = 0; rw < (row_pass ? wave_opts : 1) && st == FMM_OK; ++rw) {
                 for (int cw = 0; cw < (col_pass ? wave_opts : 1) && st == FMM_OK; ++cw) {
                     st = apply_schedule(p, tiles_opts[ti], x, rw, cw);
@@ -443,6 +504,7 @@ void fmm_batch_plan_destroy(fmm_batch_plan *p)
     if (p->tiles_dev) (void)hipFree(p->tiles_dev);
     if (p->wgoff_dev) (void)hipFree(p->wgoff_dev);
     if (p->graphs_dev) (void)hipFree(p->graphs_dev);
+    if (p->qnext_dev) (void)hipFree(p->qnext_dev);
     delete p;
 }
 

@@ -1,6 +1,8 @@
 // Plain streaming kernels that measure the HBM rate this GPU reaches on contiguous
 // traffic: a copy (read + write) and a read-only pass.  The line kernels' rates are read
-// against these ceilings as well as against the 8 TB/s specification.
+// against these ceilings as well as against the 8 TB/s specification.  A third probe
+// gathers whole rows at listed indices, the access shape of the line kernels, so that
+// hardware counters can be calibrated on a gather of known size.
 #include <hip/hip_runtime.h>
 
 #include "fmm_internal.hpp"
@@ -51,6 +53,25 @@ __global__ __launch_bounds__(kThreads) void stream_read_kernel(const u32x4_t *__
         }
 #pragma unroll
         for (int u = 0; u < kReadUnroll; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    if (acc == key) sink[0] = acc;
+}
+
+// Rows of ROWV 16-byte vectors at the listed indices: one lane group of ROWV lanes per
+// row, each lane one vector, default cache policy (as the line kernels' gathers).  Every
+// loaded word is folded into one value, stored only when it equals `key`.
+template <int ROWV>
+__global__ __launch_bounds__(kThreads) void gather_rows_kernel(const u32x4_t *__restrict__ src,
+                                                               const int32_t *__restrict__ rows, int64_t n_rows,
+                                                               uint32_t key, uint32_t *__restrict__ sink)
+{
+    constexpr int kRowsPerBlock = kThreads / ROWV;
+    const int lane = threadIdx.x % ROWV;
+    const int64_t step = (int64_t)gridDim.x * kRowsPerBlock;
+    uint32_t acc = 0;
+    for (int64_t k = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / ROWV; k < n_rows; k += step) {
+        const u32x4_t v = src[(size_t)rows[k] * ROWV + lane];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     if (acc == key) sink[0] = acc;
 }
@@ -109,6 +130,31 @@ fmm_status fmm_stream_read(const void *src, size_t bytes, uint32_t key, uint32_t
     if (e != hipSuccess) return stream_status(e);
     hipLaunchKernelGGL(stream_read_kernel, dim3(blocks), dim3(kThreads), 0, stream,
                        static_cast<const u32x4_t *>(src), n, key, sink);
+    return stream_status(hipGetLastError());
+}
+
+fmm_status fmm_stream_gather(const void *src, size_t row_bytes, const int32_t *rows, int64_t n_rows, uint32_t key,
+                             uint32_t *sink, hipStream_t stream)
+{
+    if (n_rows == 0) return FMM_OK;
+    if (!src || !rows || !sink) return FMM_ERR_NULL;
+    if (n_rows < 0) return FMM_ERR_DIM;
+    if ((uintptr_t)src % 16 != 0) return FMM_ERR_UNSUPPORTED;
+    const int rowv = (int)(row_bytes / 16);
+    if (row_bytes % 16 != 0 || rowv < 1 || rowv > 64 || (rowv & (rowv - 1)) != 0) return FMM_ERR_DIM;
+    unsigned blocks = 0;
+    hipError_t e = stream_grid((size_t)n_rows * rowv, 1, &blocks);
+    if (e != hipSuccess) return stream_status(e);
+    const u32x4_t *s = static_cast<const u32x4_t *>(src);
+    switch (rowv) {
+    case 1: hipLaunchKernelGGL(gather_rows_kernel<1>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    case 2: hipLaunchKernelGGL(gather_rows_kernel<2>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    case 4: hipLaunchKernelGGL(gather_rows_kernel<4>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    case 8: hipLaunchKernelGGL(gather_rows_kernel<8>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    case 16: hipLaunchKernelGGL(gather_rows_kernel<16>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    case 32: hipLaunchKernelGGL(gather_rows_kernel<32>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    default: hipLaunchKernelGGL(gather_rows_kernel<64>, dim3(blocks), dim3(kThreads), 0, stream, s, rows, n_rows, key, sink); break;
+    }
     return stream_status(hipGetLastError());
 }
 

@@ -27,7 +27,7 @@ from . import _capi as C
 __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to_bf16", "set_tuning",
            "device_info", "dtype_code", "BatchPlan", "gat_scores", "gat_forward", "gat_edge_values",
            "gat_forward_unfused", "gat_backward", "gat", "gat_autotune", "cg_lines", "als_residual",
-           "als_sweep", "stream_copy", "stream_read"]
+           "als_sweep", "stream_copy", "stream_read", "stream_gather"]
 
 DEFAULT_LONG_LEN = 128
 DEFAULT_CHUNK = 128
@@ -1082,6 +1082,23 @@ def stream_read(src: torch.Tensor, sink: torch.Tensor, key: int = 0x9E3779B9):
         raise ValueError("stream_read takes a contiguous GPU tensor and a one-word int32 GPU sink")
     C.call("fmm_stream_read", _ptr(src), src.numel() * src.element_size(), key, _ptr(sink), _stream())
 
+def stream_gather(src: torch.Tensor, row_bytes: int, rows: torch.Tensor, sink: torch.Tensor,
+                  key: int = 0x9E3779B9):
+    """Gather probe: read the rows `rows` (int32 device tensor) of src viewed as rows of
+    row_bytes bytes (16 * 2^k, k <= 6), one 16-byte load per lane, as the line kernels
+    gather; sink as for stream_read.  Every index is checked against src's row count here,
+    before the launch."""
+    if not (src.is_cuda and rows.is_cuda and sink.is_cuda and src.is_contiguous() and rows.is_contiguous()):
+        raise ValueError("stream_gather takes contiguous GPU tensors")
+    if rows.dtype != torch.int32 or sink.dtype != torch.int32 or sink.numel() < 1:
+        raise ValueError("rows must be int32 and sink one int32 word")
+    nbytes = src.numel() * src.element_size()
+    if row_bytes < 16 or row_bytes > 1024 or row_bytes & (row_bytes - 1) or nbytes % row_bytes:
+        raise ValueError("row_bytes must be 16 * 2^k (k <= 6) and divide src's size")
+    if rows.numel() and (int(rows.min()) < 0 or int(rows.max()) >= nbytes // row_bytes):
+        raise ValueError("a row index lies outside src")
+    C.call("fmm_stream_gather", _ptr(src), row_bytes, _ptr(rows), rows.numel(), key, _ptr(sink), _stream())
+
 
 def set_tuning(lanes: int = 0, nv: int = 0):
     """Force the lane-group shape of later launches ((0, 0) = automatic)."""
@@ -1158,10 +1175,15 @@ class BatchPlan:
         C.call("fmm_batch_autotune", self._plan, self._s(stream))
         return self.info()
 
-    def set_schedule(self, tile_nnz=8192, xcd_aware=True, row_wave=False, col_wave=False):
-        """Choose the schedule by hand: tile size, XCD-aware placement, and the
-        wavefront-per-line schedule for the row passes and for the column pass."""
-        C.call("fmm_batch_set_schedule", self._plan, tile_nnz, int(xcd_aware), int(row_wave), int(col_wave))
+    PLACE_GLOBAL, PLACE_XCD, PLACE_QUEUES = 0, 1, 2
+
+    def set_schedule(self, tile_nnz=8192, placement=PLACE_XCD, row_wave=False, col_wave=False):
+        """Choose the schedule by hand: tile size, placement (PLACE_GLOBAL: LPT over all
+        workgroups; PLACE_XCD: graphs pinned to XCDs, fixed lists; PLACE_QUEUES: graphs
+        pinned to XCDs, tiles claimed in order from a queue per XCD; a bool means XCD or
+        global), and the wavefront-per-line schedule for the row passes and for the
+        column pass."""
+        C.call("fmm_batch_set_schedule", self._plan, tile_nnz, int(placement), int(row_wave), int(col_wave))
 
     def run(self, stream=None):
         """One eager persistent launch of the current schedule."""

@@ -164,3 +164,27 @@ def test_cpu_baseline_reports_its_sample():
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
     assert "median of 3 runs" in cb["sample"] and "-march=native" in cb["build"]
     assert cb["single_thread"]["cores"] == 1 and cb["cpu_model"]
+
+
+def test_gather_summary_scales_each_row_size(tmp_path):
+    """The gather calibration reads known bytes (rows x (row bytes + 4)) against FETCH_SIZE
+    per probe kernel, and the plain copy's scale beside them."""
+    kib = bench.COPY_BYTES / 1024.0
+    rows = []
+    for k, rb in enumerate(bench.GATHER_ROW_BYTES):
+        known = (bench.PROBE_BYTES // rb) * (rb + 4)
+        name = f"void fmm::(anonymous namespace)::gather_rows_kernel<{rb // 16}>(unsigned int const*)"
+        rows += [(10 * k + i, name, known / 1024.0 / (1.0 + k)) for i in range(3)]
+    rows += [(100 + i, "__amd_rocclr_copyBuffer", kib / 2) for i in range(3)]
+    _write_pmc(str(tmp_path / "f"), "FETCH_SIZE", rows)
+    out = bench.gather_summary(str(tmp_path / "f"), str(tmp_path / "g.md"), command="rocprofv3 test")
+    assert [round(out[rb], 6) for rb in bench.GATHER_ROW_BYTES] == [1.0, 2.0, 3.0, 4.0]
+    assert "| 2.000 |" in open(tmp_path / "g.md").read()  # the copy reads half its bytes
+
+
+def test_batch_compulsory_bytes_count_every_array_once():
+    m, n, nnz, r = 1000, 800, 12000, 64
+    got = bench.batch_graph_bytes_min(m, n, nnz, r, 2, 4)
+    index = 4 * (m + 1) + 8 * nnz + 4 * (n + 1) + 8 * nnz      # CSR and CSC, values included
+    dense = 2 * m * r + 2 * n * r + 4 * m * r + 4 * m * r + 4 * m * r + 4 * n * r  # A, B, dC, C, dA, dB
+    assert got == index + dense

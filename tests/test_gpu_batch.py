@@ -53,15 +53,19 @@ def test_batch_row_block_equals_single_graph_calls(dtype):
     graphs, pats, A, B, G = _setup(dtype)
     log(f"batch row-block dtype={dtype} graphs={len(graphs)}")
     plan = F.BatchPlan(pats, A, B, G)
-    for xcd in (True, False):
-        plan.set_schedule(tile_nnz=2048, xcd_aware=xcd, row_wave=False, col_wave=False)
-        plan.run()
-        torch.cuda.synchronize()
-        single = _single(pats, A, B, G)
-        for k, (c, da, db) in enumerate(single):
-            assert torch.equal(plan.C[k], c), (k, xcd)
-            assert torch.equal(plan.dA[k], da), (k, xcd)
-            assert torch.equal(plan.dB[k], db), (k, xcd)
+    single = _single(pats, A, B, G)
+    for place in (F.BatchPlan.PLACE_XCD, F.BatchPlan.PLACE_GLOBAL, F.BatchPlan.PLACE_QUEUES):
+        plan.set_schedule(tile_nnz=2048, placement=place, row_wave=False, col_wave=False)
+        for rep in range(2):  # the queue counters start from zero again on the second launch
+            for t in plan.C + plan.dA + plan.dB:
+                t.fill_(float("nan"))
+            log(f"batch row-block placement={place} launch {rep}")
+            plan.run()
+            torch.cuda.synchronize()
+            for k, (c, da, db) in enumerate(single):
+                assert torch.equal(plan.C[k], c), (k, place, rep)
+                assert torch.equal(plan.dA[k], da), (k, place, rep)
+                assert torch.equal(plan.dB[k], db), (k, place, rep)
     _check_oracle(graphs, plan, TOL_BF16 if dtype == torch.bfloat16 else TOL_F32, "row-block")
 
 
@@ -70,29 +74,34 @@ def test_batch_wave_schedules_and_autotune(dtype):
     graphs, pats, A, B, G = _setup(dtype, seed=78)
     tol = TOL_BF16 if dtype == torch.bfloat16 else TOL_F32
     plan = F.BatchPlan(pats, A, B, G)
-    for rw, cw in ((True, False), (False, True), (True, True)):
-        log(f"batch wave rw={rw} cw={cw} dtype={dtype}")
-        plan.set_schedule(tile_nnz=8192, xcd_aware=True, row_wave=rw, col_wave=cw)
-        plan.run()
-        torch.cuda.synchronize()
-        _check_oracle(graphs, plan, tol, f"wave rw={rw} cw={cw}")
-        first = [t.clone() for t in plan.C + plan.dA + plan.dB]
-        plan.run()
-        torch.cuda.synchronize()
-        assert all(torch.equal(x, y) for x, y in zip(first, plan.C + plan.dA + plan.dB))  # repeatable
+    for place in (F.BatchPlan.PLACE_XCD, F.BatchPlan.PLACE_QUEUES):
+        for rw, cw in ((True, False), (False, True), (True, True)):
+            log(f"batch wave rw={rw} cw={cw} placement={place} dtype={dtype}")
+            plan.set_schedule(tile_nnz=8192, placement=place, row_wave=rw, col_wave=cw)
+            plan.run()
+            torch.cuda.synchronize()
+            _check_oracle(graphs, plan, tol, f"wave rw={rw} cw={cw} placement={place}")
+            first = [t.clone() for t in plan.C + plan.dA + plan.dB]
+            plan.run()
+            torch.cuda.synchronize()
+            assert all(torch.equal(x, y) for x, y in zip(first, plan.C + plan.dA + plan.dB))  # repeatable
     log("batch autotune")
     info = plan.autotune()
-    assert info["n_candidates"] >= 12 and info["best_ms"] > 0
+    assert info["n_candidates"] >= 18 and info["best_ms"] > 0
     plan.run()
     torch.cuda.synchronize()
     _check_oracle(graphs, plan, tol, "autotuned")
 
 
-def test_batch_graph_replay_matches_eager():
+@pytest.mark.parametrize("how", ["autotuned", "queues"])
+def test_batch_graph_replay_matches_eager(how):
     graphs, pats, A, B, G = _setup(torch.bfloat16, seed=79)
     plan = F.BatchPlan(pats, A, B, G)
-    log("batch autotune + capture")
-    plan.autotune()
+    log(f"batch {how} + capture")
+    if how == "autotuned":
+        plan.autotune()
+    else:  # the queue counters must be back at zero for every replay
+        plan.set_schedule(tile_nnz=2048, placement=F.BatchPlan.PLACE_QUEUES)
     plan.run()
     torch.cuda.synchronize()
     eager = [t.clone() for t in plan.C + plan.dA + plan.dB]
@@ -133,10 +142,11 @@ def test_batch_bf16_upstream_gradient():
             gate(f"{tag} graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
             dA, dB, mA, mB = ref_fusedmm_a_backward(S, g["A"], g["B"], g["G"])
             gate(f"{tag} graph {k} dB vs float32 inputs", host(plan.dB[k]), dB, mB, TOL_BF16)
-    for rw, cw in ((False, False), (True, True)):
-        log(f"batch bf16 dC rw={rw} cw={cw}")
-        plan.set_schedule(tile_nnz=2048, xcd_aware=True, row_wave=rw, col_wave=cw)
-        check(f"bf16 dC rw={rw} cw={cw}")
+    for rw, cw, place in ((False, False, F.BatchPlan.PLACE_XCD), (True, True, F.BatchPlan.PLACE_XCD),
+                          (False, False, F.BatchPlan.PLACE_QUEUES)):
+        log(f"batch bf16 dC rw={rw} cw={cw} placement={place}")
+        plan.set_schedule(tile_nnz=2048, placement=place, row_wave=rw, col_wave=cw)
+        check(f"bf16 dC rw={rw} cw={cw} placement={place}")
     log("batch bf16 dC autotune")
     plan.autotune()
     check("bf16 dC autotuned")
@@ -157,3 +167,45 @@ def test_batch_forward_only_and_oracle_bf16_rounded():
         Ar, Br = oracle.bf16_round(g["A"]), oracle.bf16_round(g["B"])
         ref, mag = ref_fusedmm_a(g["S"], Ar, Br)
         gate(f"fwd-only graph {k}", host(plan.C[k]), ref, mag, TOL_F32)
+
+
+@pytest.mark.timeout(900)
+def test_batch256_autotuned_plan_at_full_size():
+    """The bench's batch at its own size (256 ER graphs, n log-uniform in [1024, 65536],
+    degree uniform in [8, 64], r = 64, bfloat16 storage): after autotuning, the largest and
+    the smallest graphs, and the densest one, checked in full against the oracle (on the
+    bf16-rounded A and B at the float32 gate, and on the float32 originals at the bf16
+    gate)."""
+    r = 64
+    graphs = batch_er(256, r, seed=5)
+    ns = np.array([g["S"].m for g in graphs])
+    dens = np.array([g["S"].nnz / max(1, g["S"].m) for g in graphs])
+    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), int(np.argmax(dens))})
+    log(f"batch256: {len(graphs)} graphs, n {ns.min()}..{ns.max()}, checking {pick}")
+    pats = [F.Pattern.from_csr(g["S"]) for g in graphs]
+    A = [F.to_bf16(torch.from_numpy(g["A"]).cuda()) for g in graphs]
+    B = [F.to_bf16(torch.from_numpy(g["B"]).cuda()) for g in graphs]
+    G = [torch.from_numpy(g["G"]).cuda() for g in graphs]
+    plan = F.BatchPlan(pats, A, B, G)
+    log("batch256 autotune")
+    info = plan.autotune()
+    log(f"batch256 tuned: {info}")
+    side = torch.cuda.Stream()
+    plan.capture(side)
+    for t in plan.C + plan.dA + plan.dB:
+        t.fill_(float("nan"))
+    torch.cuda.synchronize()
+    plan.launch(side)
+    side.synchronize()
+    for k in pick:
+        g = graphs[k]
+        S = g["S"]
+        log(f"batch256 graph {k}: n={S.m} nnz={S.nnz}")
+        Aq, Bq = oracle.bf16_round(g["A"]), oracle.bf16_round(g["B"])
+        ref, mag = ref_fusedmm_a(S, Aq, Bq)
+        gate(f"batch256 graph {k} C", host(plan.C[k]), ref, mag, TOL_F32)
+        dA, dB, mA, mB = ref_fusedmm_a_backward(S, Aq, Bq, g["G"])
+        gate(f"batch256 graph {k} dA", host(plan.dA[k]), dA, mA, TOL_F32)
+        gate(f"batch256 graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
+        ref, mag = ref_fusedmm_a(S, g["A"], g["B"])
+        gate(f"batch256 graph {k} C vs float32 inputs", host(plan.C[k]), ref, mag, TOL_BF16)

@@ -163,3 +163,67 @@ def test_gat_backward_softmax_rows_are_shift_invariant():
     _, da1, da2, _ = oracle.gat_backward(S1, H, a1, a2, dO, slope=0.2, softmax=True)
     assert np.max(np.abs(da1)) <= 1e-12 * (1 + np.abs(da2).max() + np.abs(H).sum())
     assert np.max(np.abs(da2)) > 1e-3
+
+
+@pytest.mark.parametrize("softmax", [True, False])
+def test_gat_adjoint_magnitudes_bound_rounding_sized_perturbations(softmax):
+    """The attention adjoint's magnitude companions bound its first-order sensitivity:
+    relative perturbations of size delta in every input (H, a1, a2, dO, the stored
+    values) move each output by at most a small multiple of delta times its companion,
+    element by element.  And a relative error of 1e-3 planted in an ordinary element of
+    dH fails the 1e-5 componentwise gate (which a gate scaled by the hub rows would
+    let through)."""
+    from tests.gat_gate import gat_backward_magnitudes, kink_free
+    from tests.gates import componentwise_error
+
+    S0 = rmat(9, 8, seed=660, val_dtype=np.float64)
+    r = 16
+    H = dense_normal(S0.n, r, 661, dtype=np.float64)
+    a1 = dense_normal(1, r, 662, sigma=r ** -0.5, dtype=np.float64)[0]
+    a2 = dense_normal(1, r, 663, sigma=r ** -0.5, dtype=np.float64)[0]
+    dO = dense_normal(S0.m, r, 664, dtype=np.float64)
+    S, _ = kink_free(S0, H, a1, a2, margin=1e-3)
+    ref = oracle.gat_backward(S, H, a1, a2, dO, softmax=softmax)
+    mag = gat_backward_magnitudes(S, H, a1, a2, dO, softmax=softmax)
+    rng = np.random.default_rng(665)
+    delta = 1e-8
+
+    def jig(x):
+        return x * (1.0 + delta * rng.uniform(-1.0, 1.0, np.shape(x)))
+
+    worst = 0.0
+    for _ in range(4):
+        Sp = type(S)(S.m, S.n, S.rowptr, S.colidx, jig(S.val))
+        got = oracle.gat_backward(Sp, jig(H), jig(a1), jig(a2), jig(dO), softmax=softmax)
+        for g, e, mg in zip(got, ref, mag):
+            worst = max(worst, componentwise_error(g, e, mg) / delta)
+    assert worst <= 4.0, worst
+    # a planted error in an ordinary row (one of the lower half by max |dH|, at its
+    # best-conditioned element) is found
+    dH, dHm = ref[0], mag[0]
+    low = np.argsort(np.abs(dH).max(axis=1))[: S.n // 2]
+    ratio = np.where(dH[low] != 0, dHm[low] / np.maximum(np.abs(dH[low]), 1e-300), np.inf)
+    t, k = np.unravel_index(int(np.argmin(ratio)), ratio.shape)
+    j = int(low[t])
+    bad = dH.copy()
+    bad[j, k] *= 1.0 + 1e-3
+    assert componentwise_error(bad, dH, dHm) > 1e-5
+    assert np.abs(bad - dH).max() <= 1e-5 * np.abs(dH).max()  # the max-norm gate would pass it
+
+
+def test_kink_free_zeroes_only_near_kink_entries():
+    from tests.gat_gate import kink_free
+
+    S = rmat(10, 8, seed=670)
+    r = 8
+    H = dense_normal(S.n, r, 671)
+    a1 = dense_normal(1, r, 672, sigma=r ** -0.5)[0]
+    a2 = dense_normal(1, r, 673, sigma=r ** -0.5)[0]
+    K, k = kink_free(S, H, a1, a2, margin=1e-2)
+    s, t = oracle.gat_scores(H, a1, a2)
+    rows = np.repeat(np.arange(S.m), np.diff(S.rowptr))
+    score = s[rows] + t[S.colidx]
+    changed = K.val != S.val
+    assert k == int(changed.sum()) > 0 and np.all(K.val[changed] == 0)
+    assert np.array_equal(K.rowptr, S.rowptr) and np.array_equal(K.colidx, S.colidx)
+    assert np.abs(score[changed]).max() < np.abs(score[~changed]).max()
