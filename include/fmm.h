@@ -314,6 +314,23 @@ fmm_status fmm_fusedmm_a(const fmm_sparse *S_csr, const void *A, const void *B, 
                          size_t ws_bytes, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory: code under hipGraph / stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same result as
+ * fmm_fusedmm_a(S_csr, A, B, r, dtype, C, FMM_FUSED, NULL, ws, ...), computed by the
+ * same kernels, except that the partial sums of split lines go to a device array the
+ * library owns: FMM_NOALLOC_SCRATCH_BYTES per GPU, held by each GPU the library runs
+ * on until the process ends.  The call allocates nothing.  It returns
+ * FMM_ERR_WORKSPACE when the split partials need more than that (fmm_workspace_size
+ * with FMM_OP_FUSEDMM_A gives the need), and FMM_ERR_HIP if the array's device
+ * address cannot be found on the current device.  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents: calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race and must not be issued.
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fmm_status fmm_fusedmm_a_noalloc(const fmm_sparse *S_csr, const void *A, const void *B, int32_t r,
+                                 int32_t dtype, void *C, hipStream_t stream);
+
+/*
  * FusedMMB(S, A, B) = SpMMB(SDDMM(A, B, S), A) (Section II):
  * C'_j: = sum_i S_ij <A_i:, B_j:> A_i:, C': cols x r, computed on the CSC descriptor
  * as FusedMMA(S^T, B, A) (Section IV-B's transposed copy).  UNFUSED: the SDDMM on the

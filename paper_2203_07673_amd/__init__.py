@@ -5,6 +5,7 @@ include/fmm.h); this package is its Python binding.
 """
 from ._capi import FmmError, load as _load_library  # noqa: F401
 from .fusedmm import (  # noqa: F401
+    NOALLOC_SCRATCH_BYTES,
     BatchPlan,
     Pattern,
     als_residual,
@@ -15,6 +16,7 @@ from .fusedmm import (  # noqa: F401
     fusedmm_a,
     fusedmm_a_backward_raw,
     fusedmm_a_backward_values_raw,
+    fusedmm_a_noalloc_raw,
     fusedmm_a_raw,
     fusedmm_b,
     fusedmm_b_backward_raw,

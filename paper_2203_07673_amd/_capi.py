@@ -124,6 +124,7 @@ SIGNATURES = {
     "fmm_spmm_a": [_SP, _P, _P, _I32, _I32, _P, _D, _P, _SZ, _P],
     "fmm_spmm_b": [_SP, _P, _I32, _P, _I32, _I32, _P, _D, _P, _SZ, _P],
     "fmm_fusedmm_a": [_SP, _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P],
+    "fmm_fusedmm_a_noalloc": [_SP, _P, _P, _I32, _I32, _P, _P],
     "fmm_fusedmm_b": [_SP, _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P],
     "fmm_fusedmm_a_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _P, _P, _SZ, _P],
     "fmm_fusedmm_b_backward": [_SP, _SP, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, _P, _P, _SZ, _P],

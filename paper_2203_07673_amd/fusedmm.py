@@ -458,6 +458,23 @@ def fusedmm_a_raw(P, A, B, out=None, fused=True, R_ws=None):
     return out, R_ws
 
 
+def fusedmm_a_noalloc_raw(P, A, B, out):
+    """C = FusedMMA(S, A, B), fused, into the caller's `out`, through the library's
+    allocation-free entry point: split-line partials go to the library's own per-GPU
+    array (at most NOALLOC_SCRATCH_BYTES), so the call allocates nothing, here or in the
+    library.  Calls that overlap in time on one GPU race on that array."""
+    r = A.shape[1]
+    _check_dense("A", A, P.m, r, P.device)
+    _check_dense("B", B, P.n, r, P.device)
+    dcode, odt = _common(P, A, B)
+    _check_buf("out", out, P.device, odt, (P.m, r))
+    C.call("fmm_fusedmm_a_noalloc", ctypes.byref(P.csr), _ptr(A), _ptr(B), r, dcode, _ptr(out), _stream())
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
 def fusedmm_b_raw(P, A, B, out=None, fused=True, R_ws=None):
     """C' = FusedMMB(S, A, B) = (S * (A B^T))^T A, run as FusedMMA on the stored transpose with
     A and B interchanged (Section IV-B), no autograd.  Returns (C', R_ws), R_ws in CSR order."""
