@@ -342,6 +342,8 @@ def _role(key):
         return "split-line merge"
     if "batch_kernel<" in key:
         return "batched persistent (all passes of every graph)"
+    if "batch_queue_kernel<" in key:
+        return "batched persistent, XCD queues (all passes of every graph)"
     if "f32_to_bf16" in key:
         return ROUNDING
     return None
@@ -441,6 +443,71 @@ def load_traffic(workload_name, kernel_key):
     if not k or sf is None or sw is None:
         return None
     return (k["FETCH_SIZE"] * sf + k["WRITE_SIZE"] * sw) * 1024.0
+
+
+MARKER_KERNEL = "stream_read_kernel"
+# sources of the application passes (their counter data go stale when these change)
+APP_SRC_GLOBS = {"gat_rmat20_r128_h4": SRC_GLOBS + ("paper_2203_07673_amd/csrc/gat*.hip",),
+                 "als_er1m_d32_r128": SRC_GLOBS + ("paper_2203_07673_amd/csrc/als.hip",)}
+
+
+def marker(dev):
+    """A one-vector streaming read: a dispatch that marks region boundaries in a counter run
+    (its kernel appears nowhere else in the application benches)."""
+    import torch
+
+    import paper_2203_07673_amd as F
+
+    buf = torch.zeros(4, dtype=torch.float32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    F.stream_read(buf, sink)
+    torch.cuda.synchronize()
+
+
+def marked_summary(fetch_dir, write_dir, out_json, regions, steps, workload_name, command=""):
+    """Counter bytes per step of each marked region of a profiled run: the dispatches between
+    consecutive marker dispatches (region i lies between markers i and i + 1), FETCH and
+    WRITE scaled by the plain copies of --calibrate-copy, summed, divided by `steps`."""
+    per = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        rows = _csv_rows(d, "counter_collection.csv")
+        per[counter] = {int(r["Dispatch_Id"]): (r["Kernel_Name"], float(r["Counter_Value"]))
+                        for r in rows if r.get("Counter_Name") == counter}
+    want_kib = COPY_BYTES / 1024.0
+    out = {"command": command, "source_hash": source_hash(APP_SRC_GLOBS[workload_name]), "steps": steps,
+           "regions": {}, "scale": {}}
+    for counter, d in per.items():
+        calib = calibration_dispatches(d)
+        if not calib:
+            raise SystemExit(f"{counter}: no calibration copy found")
+        out["scale"][counter] = want_kib / (sum(d[i][1] for i in calib) / len(calib))
+        marks = sorted(i for i, (k, _) in d.items() if MARKER_KERNEL in k)
+        if len(marks) != len(regions) + 1:
+            raise SystemExit(f"{counter}: {len(marks)} markers for {len(regions)} regions")
+        for name, a, b in zip(regions, marks, marks[1:]):
+            kib = sum(v for i, (k, v) in d.items() if a < i < b)
+            reg = out["regions"].setdefault(name, {"dispatches": sum(1 for i in d if a < i < b)})
+            reg[counter + "_KiB_per_step"] = kib / steps
+    for reg in out["regions"].values():
+        reg["bytes_per_step"] = int(1024.0 * (reg["FETCH_SIZE_KiB_per_step"] * out["scale"]["FETCH_SIZE"] +
+                                              reg["WRITE_SIZE_KiB_per_step"] * out["scale"]["WRITE_SIZE"]))
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def region_traffic(workload_name, region):
+    """Counter bytes per step of a region from profiles/traffic_<workload>.json, if it was
+    taken on the current sources (else None)."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash(APP_SRC_GLOBS[workload_name]):
+        return None
+    reg = t.get("regions", {}).get(region)
+    return None if reg is None else reg["bytes_per_step"]
 
 
 def run_batch(args):
@@ -620,6 +687,22 @@ def run_gat(args):
         for h in range(heads):
             F.gat_forward(P, Hl[h], a[h][0], a[h][1], softmax=True, out=outs[h])
 
+    if args.profile_step:  # marked regions for a counter run: fp32 forward steps, then adjoint steps
+        lses_p = [torch.empty(S.m, device=dev) for _ in range(heads)]
+        for h in range(heads):
+            F.gat_forward(P, Hs[h], a[h][0], a[h][1], softmax=True, out=outs[h], lse=lses_p[h])
+        marker(dev)
+        for _ in range(args.steps):
+            step(Hs)
+        marker(dev)
+        for _ in range(args.steps):
+            for h in range(heads):
+                F.gat_backward(P, Hs[h], a[h][0], a[h][1], outs[h], dOs[h], softmax=True, lse=lses_p[h])
+        marker(dev)
+        calibrate_copy(dev)
+        print(json.dumps({"profile_step": "regions fwd_f32, bwd_f32", "steps": args.steps, "tuning": tuning}))
+        return
+
     def timeit(fn, steps, warmup):
         for _ in range(warmup):
             fn()
@@ -664,10 +747,12 @@ def run_gat(args):
     bytes32 = heads * gat_forward_bytes(n, nnz, r, 4)
     bbytes32 = heads * gat_backward_bytes(n, nnz, r, 4)
 
-    def roofline(nbytes, t, what):
+    def roofline(nbytes, t, what, region):
         achieved = nbytes / t / 1e9
+        traffic = region_traffic("gat_rmat20_r128_h4", region)
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": what,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": what,
+                "frac_counters": None if traffic is None else round(traffic / t / 1e9 / HBM_PEAK_GBS, 4),
                 "bytes_per_step": int(nbytes), "bytes_model": "gather (each stored entry fetches its rows)"}
     out = {"metric": "graph-attention forward (4 heads, softmax) ms", "workload": "gat_rmat20_r128_h4",
            "nnz": nnz, "n": n, "r": r, "heads": heads,
@@ -676,8 +761,10 @@ def run_gat(args):
            "backward_f32_ms": round(tb32 * 1e3, 4), "backward_bf16_ms": round(tb16 * 1e3, 4),
            "backward_bf16_dO_bf16_ms": round(tb16g * 1e3, 4),
            "train_step_f32_ms": round((t32 + tb32) * 1e3, 4),
-           "roofline": roofline(bytes32, t32, "fused forward of every head, fp32 (scores, line pass, merges)"),
-           "roofline_backward": roofline(bbytes32, tb32, "adjoint of every head, fp32 (row, column, da passes)"),
+           "roofline": roofline(bytes32, t32, "fused forward of every head, fp32 (scores, line pass, merges)",
+                                "fwd_f32"),
+           "roofline_backward": roofline(bbytes32, tb32, "adjoint of every head, fp32 (row, column, da passes)",
+                                         "bwd_f32"),
            "tuning": tuning}
     print(json.dumps(out), flush=True)
 
@@ -711,6 +798,14 @@ def run_als(args):
     loss0 = float(F.als_residual(P, A, B))
     F.als_sweep(P, A, B, 1e-3, 10)  # warm-up sweep
     torch.cuda.synchronize()
+    if args.profile_step:  # one marked region of sweeps for a counter run
+        marker(dev)
+        for _ in range(args.steps):
+            F.als_sweep(P, A, B, 1e-3, 10)
+        marker(dev)
+        calibrate_copy(dev)
+        print(json.dumps({"profile_step": "region sweep", "steps": args.steps}))
+        return
     sweeps = max(1, args.steps // 4)
     t0 = time.perf_counter()
     for _ in range(sweeps):
@@ -722,10 +817,12 @@ def run_als(args):
     flops = 2 * (11 * 4 * r * S.nnz + 2 * r * S.nnz)
     nbytes = als_sweep_bytes(m, n, S.nnz, r)
     achieved = nbytes / t / 1e9
+    traffic = region_traffic("als_er1m_d32_r128", "sweep")
     out = {"metric": "ALS sweep (20 batched CG iterations) ms", "workload": "als_er1m_d32_r128",
            "nnz": S.nnz, "r": r, "ms_per_sweep": round(t * 1e3, 3), "gflops": round(flops / t / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "frac_counters": None if traffic is None else round(traffic / t / 1e9 / HBM_PEAK_GBS, 4),
                         "kernel": "whole sweep (right-hand sides, Gram passes, fused CG passes)",
                         "bytes_per_sweep": int(nbytes), "bytes_model": "gather (each stored entry fetches F_j)"},
            "loss_start": loss0, "loss_after": loss, "sweeps_timed": sweeps}
@@ -914,7 +1011,11 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--counter-table", nargs="+", metavar="OUT_MD NAME=TRACE:FETCH:WRITE",
                     help="markdown table of counter-measured traffic per hot-path kernel and step variant")
-    ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16", "fused_bf16_dc_bf16"),
+    ap.add_argument("--marked-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "REGIONS"),
+                    help="counter bytes per step of the marked regions (comma-separated names) of a --profile-step "
+                         "regions run of the attention or ALS workload, and exit")
+    ap.add_argument("--profile-step", choices=("fused_f32", "unfused_f32", "fused_bf16", "fused_bf16_dc_bf16",
+                                               "regions"),
                     help="run only this step variant, for profiling (no autotune: the batch depth and split "
                          "threshold come from --tuned, else the defaults)")
     ap.add_argument("--tuned", default="",
@@ -938,6 +1039,11 @@ def main():
         return
     if args.gather_summary:
         gather_summary(*args.gather_summary, command=args.command)
+        return
+    if args.marked_summary:
+        fd, wd, oj, regs = args.marked_summary
+        wname = os.path.basename(oj)[len("traffic_"):].rsplit(".", 1)[0]
+        marked_summary(fd, wd, oj, regs.split(","), args.steps, wname, command=args.command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -1028,6 +1134,8 @@ def main():
 
     flops = 12.0 * r * nnz
     if args.profile_step:
+        if args.profile_step == "regions":
+            raise SystemExit("--profile-step regions is for the attention and ALS workloads")
         profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz)
         return
     P.autotune(A, B, G, form="a")

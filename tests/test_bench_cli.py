@@ -188,3 +188,25 @@ def test_batch_compulsory_bytes_count_every_array_once():
     index = 4 * (m + 1) + 8 * nnz + 4 * (n + 1) + 8 * nnz      # CSR and CSC, values included
     dense = 2 * m * r + 2 * n * r + 4 * m * r + 4 * m * r + 4 * m * r + 4 * n * r  # A, B, dC, C, dA, dB
     assert got == index + dense
+
+
+def test_marked_summary_counts_only_the_marked_regions(tmp_path):
+    """Bytes per step of each region = the dispatches strictly between its two markers,
+    FETCH x 2 and WRITE x 1 (the copy calibration), divided by the step count."""
+    kib = bench.COPY_BYTES / 1024.0
+    mk = "fmm::(anonymous namespace)::stream_read_kernel(unsigned int __vector(4) const*, unsigned long)"
+    k = "void fmm::gat_kernel<float, 32>(fmm::GatArgs)"
+    cp = "__amd_rocclr_copyBuffer"
+    fetch = [(1, k, 999.0), (2, mk, 0.1), (3, k, 10.0), (4, k, 30.0), (5, mk, 0.1), (6, k, 7.0), (7, mk, 0.1)] + \
+        [(20 + i, cp, kib / 2) for i in range(3)]
+    write = [(1, k, 999.0), (2, mk, 0.0), (3, k, 1.0), (4, k, 3.0), (5, mk, 0.0), (6, k, 5.0), (7, mk, 0.0)] + \
+        [(20 + i, cp, kib) for i in range(3)]
+    _write_pmc(str(tmp_path / "f"), "FETCH_SIZE", fetch)
+    _write_pmc(str(tmp_path / "w"), "WRITE_SIZE", write)
+    out = str(tmp_path / "traffic_gat_rmat20_r128_h4.json")
+    bench.marked_summary(str(tmp_path / "f"), str(tmp_path / "w"), out, ["fwd_f32", "bwd_f32"], 2,
+                         "gat_rmat20_r128_h4", command="rocprofv3 test")
+    t = json.load(open(out))
+    assert t["regions"]["fwd_f32"]["bytes_per_step"] == int(1024 * ((10 + 30) * 2 + (1 + 3)) / 2)
+    assert t["regions"]["bwd_f32"]["bytes_per_step"] == int(1024 * (7 * 2 + 5) / 2)
+    assert t["regions"]["fwd_f32"]["dispatches"] == 2

@@ -49,6 +49,7 @@ def test_cg_lines_parity(dtype, iters, split):
         F.cg_lines(P, orient, Fd, dev(rhs), lam, iters, X)
         ref = oracle.cg_lines(pat, Fq, rhs, lam, iters, X0)
         err = _rowrel(host(X), ref)
+        log(f"cg dtype={dtype} iters={iters} split={split} orient={orient}: per-line error {err:.3e}")
         assert err <= 1e-4, (orient, err)
 
 
@@ -71,6 +72,7 @@ def test_cg_lines_parity_wide_rows(dtype, r):
     F.cg_lines(P, C.FMM_CSR, Fd, dev(rhs), lam, iters, X)
     ref = oracle.cg_lines(S, Fq, rhs, lam, iters, X0)
     err = _rowrel(host(X), ref)
+    log(f"cg wide dtype={dtype} r={r}: per-line error {err:.3e}")
     assert err <= 1e-4, err
 
 
