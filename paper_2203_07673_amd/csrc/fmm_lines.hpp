@@ -516,12 +516,16 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     constexpr bool kHeld2 = (OP == OP_FUSED1S);
     constexpr bool kTwo = (OP == OP_SPMM2 || OP == OP_FUSED2);
 
+    // A line without entries needs no held row (its outputs are zeros), except a CG step,
+    // whose update uses the direction itself; skipping the load saves a row read per empty
+    // line (half the lines of an R-MAT pattern).
+    const bool want_held = OP == OP_CG || begin < end;
     Acc h[E];
     if constexpr (kHeld) {
         const TH *__restrict__ Hrow = static_cast<const TH *>(o.H) + (size_t)line * r;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if (act[v]) {
+            if (act[v] && want_held) {
                 Ld<TH, VW, Acc>::template run<kNtHeld>(Hrow + off[v], h + v * VW);
             } else {
 #pragma unroll
@@ -535,7 +539,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         const TG2 *__restrict__ H2row = static_cast<const TG2 *>(o.H2) + (size_t)line * r;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if (act[v]) {
+            if (act[v] && want_held) {
                 Ld<TG2, VW, Acc>::template run<kNtHeld>(H2row + off[v], h2 + v * VW);
             } else {
 #pragma unroll

@@ -99,3 +99,17 @@ def test_rmat_properties(scale, ef, seed):
     for i in range(n):
         row = S.colidx[S.rowptr[i]:S.rowptr[i + 1]]
         assert (np.diff(row) > 0).all()
+
+
+def test_workload_cache_gives_the_same_arrays(tmp_path, monkeypatch):
+    from workloads import workload
+
+    fresh = workload("er4096_d32_r32")
+    monkeypatch.setenv("FMM_WORKLOAD_CACHE", str(tmp_path))
+    first, again = workload("er4096_d32_r32"), workload("er4096_d32_r32")  # writes, then maps
+    for w in (first, again):
+        for k in ("rowptr", "colidx", "val"):
+            assert np.array_equal(np.asarray(getattr(w["S"], k)), np.asarray(getattr(fresh["S"], k)))
+        for k in "ABG":
+            assert w[k].dtype == fresh[k].dtype and np.array_equal(w[k], fresh[k])
+        assert w["r"] == fresh["r"] and w["S"].m == fresh["S"].m and w["S"].nnz == fresh["S"].nnz

@@ -3,8 +3,9 @@
 CG is an iteration: the GPU (float32) and the oracle (float64) follow the same
 recurrence, and on a well-conditioned system (lambda = 1, F ~ N(0, 1/r), so each
 line's matrix has eigenvalues of order 1-3) their iterates stay within a few
-units of float32 rounding times the condition number and the step count; the
-gate below (1e-4 of the iterate's size per line) leaves a wide margin for that.
+units of float32 rounding times the condition number and the step count.  The gate
+is the float32 tolerance, 1e-5 of the iterate's size per line, after 1, 5 and 10
+steps (on MI355X the largest error is 5.9e-6, after 10 steps).
 """
 import numpy as np
 import pytest
@@ -17,6 +18,8 @@ from tests.gpu_helpers import dev, host, log
 from workloads import CsrPattern, dense_normal, er_exact_degree, rmat
 
 pytestmark = pytest.mark.gpu
+
+TOL_CG = 1e-5  # per line, relative to the line's largest iterate element
 
 
 def _rowrel(got, ref):
@@ -50,7 +53,7 @@ def test_cg_lines_parity(dtype, iters, split):
         ref = oracle.cg_lines(pat, Fq, rhs, lam, iters, X0)
         err = _rowrel(host(X), ref)
         log(f"cg dtype={dtype} iters={iters} split={split} orient={orient}: per-line error {err:.3e}")
-        assert err <= 1e-4, (orient, err)
+        assert err <= TOL_CG, (orient, err)
 
 
 @pytest.mark.parametrize("r", [128, 512])
@@ -73,7 +76,7 @@ def test_cg_lines_parity_wide_rows(dtype, r):
     ref = oracle.cg_lines(S, Fq, rhs, lam, iters, X0)
     err = _rowrel(host(X), ref)
     log(f"cg wide dtype={dtype} r={r}: per-line error {err:.3e}")
-    assert err <= 1e-4, err
+    assert err <= TOL_CG, err
 
 
 def test_residual_and_als_sweeps_reduce_loss():

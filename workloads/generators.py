@@ -17,6 +17,8 @@ Conventions shared by every generator:
 from __future__ import annotations
 
 import hashlib
+import json
+import os
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
@@ -197,7 +199,35 @@ WORKLOADS = {
 
 
 def workload(name: str, dtype=np.float32, scale_override: Optional[int] = None) -> dict:
-    """Pattern S plus dense A (m x r), B (n x r) and upstream gradient G (m x r)."""
+    """Pattern S plus dense A (m x r), B (n x r) and upstream gradient G (m x r).
+
+    With the environment variable FMM_WORKLOAD_CACHE naming a directory, the arrays are
+    saved there on first use and memory-mapped on later calls (profiling runs that start
+    many processes on one workload); the arrays are the same either way."""
+    cache = os.environ.get("FMM_WORKLOAD_CACHE")
+    if cache and scale_override is None:
+        d = os.path.join(cache, f"{name}_{np.dtype(dtype).name}")
+        keys = ("rowptr", "colidx", "val", "A", "B", "G")
+        if os.path.exists(os.path.join(d, "done")):
+            with open(os.path.join(d, "meta.json")) as fh:
+                meta = json.load(fh)
+            arr = {k: np.load(os.path.join(d, k + ".npy"), mmap_mode="r") for k in keys}
+            S = CsrPattern(meta["m"], meta["n"], arr["rowptr"], arr["colidx"], arr["val"], meta=meta["meta"])
+            return {"name": name, "S": S, "A": arr["A"], "B": arr["B"], "G": arr["G"], "r": meta["r"],
+                    "sigma": meta["sigma"]}
+        w = _generate(name, dtype)
+        os.makedirs(d, exist_ok=True)
+        S = w["S"]
+        for k, a in zip(keys, (S.rowptr, S.colidx, S.val, w["A"], w["B"], w["G"])):
+            np.save(os.path.join(d, k + ".npy"), np.ascontiguousarray(a))
+        with open(os.path.join(d, "meta.json"), "w") as fh:
+            json.dump({"m": S.m, "n": S.n, "r": w["r"], "sigma": w["sigma"], "meta": S.meta}, fh)
+        open(os.path.join(d, "done"), "w").close()
+        return w
+    return _generate(name, dtype, scale_override)
+
+
+def _generate(name: str, dtype=np.float32, scale_override: Optional[int] = None) -> dict:
     w = dict(WORKLOADS[name])
     seed = w["seed"]
     if w["kind"] == "er":
