@@ -415,14 +415,42 @@ def counter_table(out_md, runs, command=""):
     print("\n".join(lines))
 
 
+def timed_region(trace_dir):
+    """Per-kernel launch count and average duration (us) of the dispatches between the first
+    two marker launches of a kernel trace (the bench's timed steps, warm-up included), or
+    None when the trace holds no such pair."""
+    disp = _csv_rows(trace_dir, "kernel_trace.csv")
+    if not disp:
+        return None
+    disp.sort(key=lambda r: int(r["Start_Timestamp"]))
+    marks = [k for k, r in enumerate(disp) if MARKER_KERNEL in r["Kernel_Name"]][:2]
+    if len(marks) < 2:
+        return None
+    out = {}
+    for r in disp[marks[0] + 1:marks[1]]:
+        k = _short_kernel(r["Kernel_Name"])
+        out.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return {k: (len(v), sum(v) / len(v)) for k, v in out.items()}
+
+
 def trace_summary(trace_dir, out_md, command=""):
     rows = _csv_rows(trace_dir, "kernel_stats.csv")
-    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
-             "| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
+    timed = timed_region(trace_dir)
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", ""]
+    if timed:
+        lines += ["Columns *timed calls* and *timed avg us*: the launches between the two marker launches that "
+                  "bracket the bench's timed fused float32 steps (warm-up included). The other columns cover every "
+                  "launch of the run, autotune candidates included.", ""]
+    lines += ["| kernel | calls | avg us | min us | max us | total % |" + (" timed calls | timed avg us |" if timed else ""),
+              "|---|---|---|---|---|---|" + ("---|---|" if timed else "")]
     for r in sorted(rows, key=lambda r: -float(r.get("TotalDurationNs", 0))):
-        lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        k = _short_kernel(r["Name"])
+        extra = ""
+        if timed:
+            extra = f" {timed[k][0]} | {timed[k][1]:.1f} |" if k in timed else " | |"
+        lines.append(f"| `{k}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
-                     f"{float(r['Percentage']):.2f} |")
+                     f"{float(r['Percentage']):.2f} |" + extra)
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -835,8 +863,21 @@ def restore_tuning(P, tuning):
 
 
 def tuning_arg(tuning):
-    """--tuned form of P.tuning: csr=VARIANT:LONG_LEN:ORDER,csc=... (LONG_LEN 0 = no split)."""
-    return ",".join(f"{k}={t['variant']}:{t['long_len'] or 0}:{int(t['line_order'])}" for k, t in tuning.items())
+    """--tuned form of P.tuning: csr=VARIANT:LONG_LEN:ORDER:HINTS,csc=... (LONG_LEN 0 = no split,
+    HINTS = hot minor lines of the gather hints, 0 = none)."""
+    return ",".join(f"{k}={t['variant']}:{t['long_len'] or 0}:{int(t['line_order'])}:{t.get('gather_hints') or 0}"
+                    for k, t in tuning.items())
+
+
+def parse_tuning_arg(arg):
+    """Inverse of tuning_arg (a missing HINTS field means none)."""
+    tuning = {}
+    for part in arg.split(","):
+        k, v = part.split("=")
+        f = [int(x) for x in v.split(":")]
+        tuning[k] = {"variant": f[0], "long_len": f[1] or None, "line_order": bool(f[2]),
+                     "gather_hints": (f[3] if len(f) > 3 else 0) or None}
+    return tuning
 
 
 def calibrate_copy(dev):
@@ -972,12 +1013,7 @@ def profile_step(args, F, P, A, B, make_step, time_steps, flops, nnz):
 
     dev = A.device
     if args.tuned:
-        tuning = {}
-        for part in args.tuned.split(","):
-            k, v = part.split("=")
-            var, ll, lo = (int(x) for x in v.split(":"))
-            tuning[k] = {"variant": var, "long_len": ll or None, "line_order": bool(lo)}
-        restore_tuning(P, tuning)
+        restore_tuning(P, parse_tuning_arg(args.tuned))
     if args.profile_step == "fused_f32":
         step = make_step(A, B, fused=True)
     elif args.profile_step == "unfused_f32":
@@ -1019,9 +1055,9 @@ def main():
                     help="run only this step variant, for profiling (no autotune: the batch depth and split "
                          "threshold come from --tuned, else the defaults)")
     ap.add_argument("--tuned", default="",
-                    help="csr=VARIANT:LONG_LEN:ORDER,csc=VARIANT:LONG_LEN:ORDER as a bench run's autotune chose "
-                         "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1); for batch256_r64 "
-                         "TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE")
+                    help="csr=VARIANT:LONG_LEN:ORDER:HINTS,csc=... as a bench run's autotune chose "
+                         "them (config.tuning_arg; LONG_LEN 0 = no split schedule, ORDER 0/1, HINTS 0 = no gather "
+                         "hints); for batch256_r64 TILE_NNZ:XCD_AWARE:ROW_WAVE:COL_WAVE")
     ap.add_argument("--calibrate-gather", action="store_true",
                     help="run only the gather probes of known size and the plain copies (for a --pmc run)")
     ap.add_argument("--gather-summary", nargs=2, metavar=("FETCH_DIR", "OUT_MD"),
@@ -1144,7 +1180,9 @@ def main():
     step_f32 = make_step(A, B, fused=True)
     log(f"timing fused f32: warmup {args.warmup}, steps {args.steps}")
     step_ms = []
+    marker(dev)  # brackets the timed steps' dispatches in a kernel trace (outside the timed region)
     t_step, kt = time_steps(step_f32, args.steps, args.warmup, step_ms=step_ms)
+    marker(dev)
     gflops = flops / t_step / 1e9
     # sampled outputs of the last timed step of each variant, for the error report
     colptr_h = np.concatenate([[0], np.cumsum(np.bincount(S.colidx, minlength=n))])

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 3
+#define FMM_ABI_VERSION 4
 
 typedef enum fmm_status {
     FMM_OK = 0,
@@ -102,6 +102,13 @@ typedef enum fmm_orient { FMM_CSR = 0, FMM_CSC = 1 } fmm_orient;
  * bit-identical with and without it.  Grouping lines of similar length into the same
  * wavefront keeps a wavefront from idling behind its longest line.
  *
+ * hot: optional gather hint per stored entry (orientation order, from fmm_gather_hints).
+ * An entry with hot[p] == 0 gathers its dense row with the streaming (nontemporal) cache
+ * policy, any other with the default policy; NULL gathers every row with the default
+ * policy.  Rows of hub lines, which many entries gather, then keep their place in L2
+ * and the MALL instead of being displaced by rows that are gathered once.  It changes
+ * only the cache policy of loads, so results are bit-identical with and without it.
+ *
  * variant: how many stored entries a lane group keeps in flight per batch (FMM_VARIANT_*).
  * Deep batches suit long, uniform lines; shallow ones use fewer registers, so more lines
  * are in flight at once, which suits many short lines.  FMM_VARIANT_AUTO picks from the
@@ -127,6 +134,7 @@ typedef struct fmm_sparse {
     const int32_t *chunks;     /* [3*n_chunks]: line, begin position, end position       */
     const int32_t *splits;     /* [3*n_splits]: line, first chunk, chunk count           */
     const int32_t *order;      /* [major extent] line processing order, or NULL          */
+    const uint8_t *hot;        /* [nnz] gather hint per stored entry, or NULL            */
 } fmm_sparse;
 
 /* ---------------------------------------------------------------- diagnostics */
@@ -250,6 +258,22 @@ fmm_status fmm_gather_values(const int32_t *perm, const void *src, int32_t val_d
 fmm_status fmm_line_order_workspace(int32_t nlines, size_t *bytes);
 fmm_status fmm_line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, int32_t *order, void *ws,
                           size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Gather hints (see fmm_sparse.hot) for the descriptor S: hot[p] = 1 when the minor line
+ * of stored entry p (its column for a CSR descriptor, its row for a CSC one) is among the
+ * `top` longest minor lines, else 0.  minor_ptr is the other orientation's pointer array
+ * (n_minor + 1 entries: colptr for a CSR S, rowptr for a CSC S), whose line lengths are
+ * the minor lines' entry counts; every line as long as the top-th longest counts as one
+ * of them.  top <= 0 marks no entry hot; top >= n_minor marks every entry hot.  hot:
+ * S->nnz bytes, caller-owned.  Synchronous: the length threshold is found on the host
+ * from a copy of minor_ptr.  The paper keeps reused rows in cache by blocking the loop
+ * over stored entries (Section III-A); the hint keeps the most reused rows there by cache
+ * policy instead, without reordering any work.  Pattern autotuning decides per
+ * orientation whether to use it.
+ */
+fmm_status fmm_gather_hints(const fmm_sparse *S, const int32_t *minor_ptr, int32_t n_minor, int32_t top,
+                            uint8_t *hot, hipStream_t stream);
 
 /* Round float32 to bfloat16 storage (nearest, ties to even; NaN -> 0x7FC0). */
 fmm_status fmm_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t stream);

@@ -49,6 +49,7 @@ class fmm_sparse(ctypes.Structure):
         ("chunks", ctypes.c_void_p),
         ("splits", ctypes.c_void_p),
         ("order", ctypes.c_void_p),
+        ("hot", ctypes.c_void_p),
     ]
 
 
@@ -105,6 +106,7 @@ SIGNATURES = {
     "fmm_stream_copy": [_P, _P, _SZ, _P],
     "fmm_stream_read": [_P, _SZ, ctypes.c_uint32, _P, _P],
     "fmm_stream_gather": [_P, _SZ, _P, _I64, ctypes.c_uint32, _P, _P],
+    "fmm_gather_hints": [_SP, _P, _I32, _I32, _P, _P],
     "fmm_validate": [_SP, _P],
     "fmm_csr_to_csc_workspace": [_I32, _I32, _I32, ctypes.POINTER(_SZ)],
     "fmm_csr_to_csc": [_I32, _I32, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P],

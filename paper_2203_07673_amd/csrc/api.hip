@@ -5,7 +5,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <functional>
+#include <vector>
 
 #include "fmm.h"
 #include "fmm_internal.hpp"
@@ -148,6 +150,7 @@ LineArgs base_args(const fmm_sparse *S, int32_t r, void *ws)
     a.n_chunks = S->n_chunks;
     a.chunks = S->chunks;
     a.order = S->order;
+    a.hot = S->hot;
     a.partial = ws;
     a.beta = 0.0;
     return a;
@@ -420,6 +423,32 @@ fmm_status fmm_line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, 
     if (!ptr || !order) return FMM_ERR_NULL;
     if (!ws || ws_bytes < line_order_workspace_bytes(nlines) || (uintptr_t)ws % 16 != 0) return FMM_ERR_WORKSPACE;
     FMM_HIP(line_order(ptr, nlines, long_len, order, ws, stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_gather_hints(const fmm_sparse *S, const int32_t *minor_ptr, int32_t n_minor, int32_t top,
+                            uint8_t *hot, hipStream_t stream)
+{
+    FMM_TRY(check_sparse(S, -1));
+    const int32_t minor = S->orient == FMM_CSR ? S->cols : S->rows;
+    if (n_minor != minor) return FMM_ERR_DIM;
+    if (S->nnz == 0) return FMM_OK;
+    if (!minor_ptr || !hot) return FMM_ERR_NULL;
+    // the length of the top-th longest minor line is the threshold (0: every line is hot)
+    int32_t min_len = 0;
+    if (top <= 0) {
+        min_len = INT32_MAX;
+    } else if (top < n_minor) {
+        std::vector<int32_t> ptr((size_t)n_minor + 1);
+        FMM_HIP(hipMemcpyAsync(ptr.data(), minor_ptr, ptr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        FMM_HIP(hipStreamSynchronize(stream));
+        std::vector<int32_t> len((size_t)n_minor);
+        for (int32_t j = 0; j < n_minor; ++j) len[j] = ptr[j + 1] - ptr[j];
+        std::nth_element(len.begin(), len.begin() + (top - 1), len.end(), std::greater<int32_t>());
+        min_len = std::max<int32_t>(1, len[top - 1]);
+    }
+    FMM_HIP(gather_hints(S->idx, minor_ptr, S->nnz, min_len, hot, stream));
+    FMM_HIP(hipStreamSynchronize(stream));
     return FMM_OK;
 }
 

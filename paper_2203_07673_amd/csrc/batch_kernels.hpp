@@ -36,6 +36,7 @@ __device__ __forceinline__ void run_tile(const BatchGraphDev *__restrict__ graph
     LineOperands o;
     o.wv1 = o.wv2 = nullptr;
     o.wperm = o.operm = nullptr;
+    o.hot = nullptr;
     o.R = nullptr;
     o.r = r;
     o.beta = 0.0;

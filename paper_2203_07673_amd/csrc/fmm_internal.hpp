@@ -57,6 +57,8 @@ hipError_t csr_to_csc(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, 
 hipError_t validate(int32_t nmajor, int32_t nminor, int32_t nnz, const int32_t *ptr, const int32_t *idx,
                     int32_t *flag_dev, hipStream_t s);
 hipError_t gather_values(const int32_t *perm, const void *src, void *dst, int32_t nnz, int val_bytes, hipStream_t s);
+hipError_t gather_hints(const int32_t *idx, const int32_t *minor_ptr, int32_t nnz, int32_t min_len, uint8_t *hot,
+                        hipStream_t s);
 size_t line_order_workspace_bytes(int64_t nlines);
 hipError_t line_order(const int32_t *ptr, int32_t nlines, int32_t long_len, int32_t *order, void *ws, hipStream_t s);
 size_t schedule_workspace_bytes(int64_t nmajor);

@@ -31,6 +31,10 @@
 // sum, so no broadcast is needed and no LDS is touched.  U entries are loaded
 // before any of them is reduced, to keep U row gathers in flight per group.
 //
+// Gather hints: with a per-entry hint array, entries whose hint is 0 gather their row
+// with the streaming (nontemporal) policy, so rows gathered once do not displace the
+// rows of hub lines, which many entries gather, from L2 and the MALL.
+//
 // Long lines: with a split schedule, lines longer than long_len are skipped by
 // the line groups and processed as chunks (line, begin, end) whose partial
 // r-vectors go to a workspace; merge_kernel adds them in chunk order.  Chunk
@@ -49,6 +53,7 @@ typedef uint16_t bf16_t;
 static __device__ const float kUnitF[1] = {1.0f};
 static __device__ const double kUnitD[1] = {1.0};
 static __device__ const int32_t kZeroIdx[1] = {0};
+static __device__ const uint8_t kHotByte[1] = {1};
 template <class Acc> __device__ __forceinline__ const Acc *unit_value();
 template <> __device__ __forceinline__ const float *unit_value<float>() { return kUnitF; }
 template <> __device__ __forceinline__ const double *unit_value<double>() { return kUnitD; }
@@ -83,6 +88,7 @@ struct LineArgs {
     void *partial;        // n_chunks x r (Acc)
     int32_t uclass;       // batch depth class, 1 (deep) .. 3 (shallow)
     const int32_t *order; // line processing order (a permutation of the lines), NULL = index order
+    const uint8_t *hot;   // per-entry gather hint in orientation order (0: streaming policy), NULL = all 1
 };
 
 // ------------------------------------------------------------------ conversions
@@ -193,6 +199,13 @@ template <> struct Ld<double, 2, double> {
     }
 };
 
+// Fused multiply-add written out, so that every kernel that runs a line (the line kernel
+// and the batched kernels, each compiled on its own) rounds each update the same way:
+// the compiler's own contraction of an expression such as x += a*b + c*d may differ
+// between instantiations.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class Acc, int VW> struct St;
 template <> struct St<float, 1> {
     template <bool NT = false> static __device__ __forceinline__ void run(float *p, const float *v) {
@@ -235,6 +248,7 @@ template <> struct Raw<float, 1> {
     float x;
     __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const float *p) { x = ld_hint<kNtGather>(p); }
+    __device__ __forceinline__ void load_nt(const float *p) { x = ld_hint<true>(p); }
     __device__ __forceinline__ void zero() { x = 0.f; }
     __device__ __forceinline__ float get(int) const { return x; }
 };
@@ -248,6 +262,10 @@ template <> struct Raw<float, 4> {
         } else {
             x = *reinterpret_cast<const float4 *>(p);
         }
+    }
+    __device__ __forceinline__ void load_nt(const float *p) {
+        const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+        x = make_float4(v.x, v.y, v.z, v.w);
     }
     __device__ __forceinline__ void zero() { x = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
@@ -266,6 +284,12 @@ template <> struct Raw<float, 8> {
             y = reinterpret_cast<const float4 *>(p)[1];
         }
     }
+    __device__ __forceinline__ void load_nt(const float *p) {
+        const f32x4_t v = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p));
+        const f32x4_t w = ld_hint<true>(reinterpret_cast<const f32x4_t *>(p) + 1);
+        x = make_float4(v.x, v.y, v.z, v.w);
+        y = make_float4(w.x, w.y, w.z, w.w);
+    }
     __device__ __forceinline__ void zero() { x = y = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ __forceinline__ float get(int e) const {
         const float4 &q = e < 4 ? x : y;
@@ -283,6 +307,10 @@ template <> struct Raw<bf16_t, 8> {
             x = *reinterpret_cast<const uint4 *>(p);
         }
     }
+    __device__ __forceinline__ void load_nt(const bf16_t *p) {
+        const u32x4_t v = ld_hint<true>(reinterpret_cast<const u32x4_t *>(p));
+        x = make_uint4(v.x, v.y, v.z, v.w);
+    }
     __device__ __forceinline__ void zero() { x = make_uint4(0u, 0u, 0u, 0u); }
     // Make the packed words opaque to the optimiser, so elements widened for the dot
     // product are widened again for the update instead of staying live in between.
@@ -296,6 +324,7 @@ template <> struct Raw<double, 1> {
     double x;
     __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const double *p) { x = p[0]; }
+    __device__ __forceinline__ void load_nt(const double *p) { x = ld_hint<true>(p); }
     __device__ __forceinline__ void zero() { x = 0.0; }
     __device__ __forceinline__ double get(int) const { return x; }
 };
@@ -303,6 +332,10 @@ template <> struct Raw<double, 2> {
     double2 x;
     __device__ __forceinline__ void pin() {}
     __device__ __forceinline__ void load(const double *p) { x = *reinterpret_cast<const double2 *>(p); }
+    __device__ __forceinline__ void load_nt(const double *p) {
+        const f64x2_t v = ld_hint<true>(reinterpret_cast<const f64x2_t *>(p));
+        x = make_double2(v.x, v.y);
+    }
     __device__ __forceinline__ void zero() { x = make_double2(0.0, 0.0); }
     __device__ __forceinline__ double get(int e) const { return e == 0 ? x.x : x.y; }
 };
@@ -420,6 +453,7 @@ struct LineOperands {
     const void *G1;
     const void *G2;
     const void *H2;  // OP_FUSED1S second held matrix
+    const uint8_t *hot;  // per-entry gather hint (NULL: every row with the default policy)
     void *R;         // per-entry output (nnz): OP_SDDMM, OP_FUSED1S
     float *cg_X, *cg_R, *cg_P, *cg_rr;  // OP_CG
     float cg_lambda;
@@ -563,17 +597,20 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     const int32_t w2s = wv2 ? 1 : 0;
     const int32_t *perm_p = wperm ? wperm : zero_index();
     const int32_t ps = wperm ? 1 : 0;
+    const uint8_t *hot_p = o.hot ? o.hot : kHotByte;
+    const int32_t hs = o.hot ? 1 : 0;
     const bool partial = C < L * NV;  // some lanes own no vector of r (uniform)
 
     // Per-entry operands of one batch (column indices and weights).  Entries past `end`
     // read the last entry of the line, so every load is in bounds.
-    auto load_meta = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2) {
+    auto load_meta = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2, uint32_t *hv) {
         constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t p = p0 + u;
             const int32_t pc = (FULL || p < end) ? p : end - 1;
             j[u] = ld_hint<kNtMeta>(idx + pc);
+            hv[u] = hot_p[pc * hs];
             const Acc base = ld_hint<kNtMeta>(val_p + pc * vs);
             if constexpr (OP == OP_SPMM1 || OP == OP_SPMM2) {
                 const int32_t q = perm_p[pc * ps] + pc * (1 - ps);
@@ -594,10 +631,10 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     // operands of the batch at `pn` are loaded into (jn, w1n, w2n), so that they arrive
     // while this batch waits for its rows (PF; the batched persistent kernel, whose rows
     // are mostly L2 hits, runs faster without it).
-    auto run_batch = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2, int32_t pn, int32_t *jn,
-                         Acc *w1n, Acc *w2n) {
+    auto run_batch = [&](int32_t p0, auto full_tag, int32_t *j, Acc *w1, Acc *w2, uint32_t *hv, int32_t pn,
+                         int32_t *jn, Acc *w1n, Acc *w2n, uint32_t *hvn) {
         constexpr bool FULL = decltype(full_tag)::value;
-        if constexpr (!PF) load_meta(p0, full_tag, j, w1, w2);
+        if constexpr (!PF) load_meta(p0, full_tag, j, w1, w2, hv);
         bool okv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) okv[u] = FULL || p0 + u < end;
@@ -611,13 +648,18 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
             for (int v = 0; v < NV; ++v) {
                 const int o = act[v] ? off[v] : 0;  // idle lanes read a valid spot, zeroed below
                 if (FULL || okv[u]) {
-                    g1[u][v].load(row1 + o);
-                    if constexpr (kTwo) g2[u][v].load(row2 + o);
+                    if (hv[u]) {
+                        g1[u][v].load(row1 + o);
+                        if constexpr (kTwo) g2[u][v].load(row2 + o);
+                    } else {
+                        g1[u][v].load_nt(row1 + o);
+                        if constexpr (kTwo) g2[u][v].load_nt(row2 + o);
+                    }
                 }
             }
         }
         if constexpr (PF) {
-            if (pn < end) load_meta(pn, std::false_type{}, jn, w1n, w2n);  // one clamped form: no divergence
+            if (pn < end) load_meta(pn, std::false_type{}, jn, w1n, w2n, hvn);  // one clamped form: no divergence
         }
         if (partial) {
 #pragma unroll
@@ -639,9 +681,10 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
                         if constexpr (OP == OP_SPMM2)
-                            acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e)) + w2[u] * Acc(g2[u][v].get(e));
+                            acc[v * VW + e] = fmadd(w2[u], Acc(g2[u][v].get(e)),
+                                                    fmadd(w1[u], Acc(g1[u][v].get(e)), acc[v * VW + e]));
                         else
-                            acc[v * VW + e] += w1[u] * Acc(g1[u][v].get(e));
+                            acc[v * VW + e] = fmadd(w1[u], Acc(g1[u][v].get(e)), acc[v * VW + e]);
                     }
             }
         } else if constexpr (OP == OP_FUSED2) {
@@ -653,8 +696,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
-                        s1 += h[v * VW + e] * Acc(g2[u][v].get(e));
-                        s2 += h[v * VW + e] * Acc(g1[u][v].get(e));
+                        s1 = fmadd(h[v * VW + e], Acc(g2[u][v].get(e)), s1);
+                        s2 = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s2);
                     }
                 d1[u] = s1;
                 d2[u] = s2;
@@ -679,7 +722,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
-                        acc[v * VW + e] += c1 * Acc(g1[u][v].get(e)) + c2 * Acc(g2[u][v].get(e));
+                        acc[v * VW + e] = fmadd(c2, Acc(g2[u][v].get(e)),
+                                                fmadd(c1, Acc(g1[u][v].get(e)), acc[v * VW + e]));
             }
         } else {
             Acc d[U], dv[kHeld2 ? U : 1];
@@ -690,8 +734,8 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
-                        s += h[v * VW + e] * Acc(g1[u][v].get(e));
-                        if constexpr (kHeld2) s2 += h2[v * VW + e] * Acc(g1[u][v].get(e));
+                        s = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s);
+                        if constexpr (kHeld2) s2 = fmadd(h2[v * VW + e], Acc(g1[u][v].get(e)), s2);
                     }
                 d[u] = s;
                 if constexpr (kHeld2) dv[u] = s2;
@@ -732,7 +776,7 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
 #pragma unroll
-                        for (int e = 0; e < VW; ++e) acc[v * VW + e] += c * Acc(g1[u][v].get(e));
+                        for (int e = 0; e < VW; ++e) acc[v * VW + e] = fmadd(c, Acc(g1[u][v].get(e)), acc[v * VW + e]);
                 }
             }
         }
@@ -741,20 +785,22 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
     {
         int32_t j[U], jn[U];
         Acc w1[U], w2[U], w1n[U], w2n[U];
+        uint32_t hv[U], hvn[U];
         int32_t p0 = begin + gidx * U;
         if constexpr (PF) {
-            if (p0 < end) load_meta(p0, std::false_type{}, j, w1, w2);
+            if (p0 < end) load_meta(p0, std::false_type{}, j, w1, w2, hv);
         }
         for (; p0 < end; p0 += U * GPL) {
             const int32_t pn = p0 + U * GPL;
-            if (p0 + U <= end) run_batch(p0, std::true_type{}, j, w1, w2, pn, jn, w1n, w2n);
-            else run_batch(p0, std::false_type{}, j, w1, w2, pn, jn, w1n, w2n);
+            if (p0 + U <= end) run_batch(p0, std::true_type{}, j, w1, w2, hv, pn, jn, w1n, w2n, hvn);
+            else run_batch(p0, std::false_type{}, j, w1, w2, hv, pn, jn, w1n, w2n, hvn);
             if constexpr (PF) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     j[u] = jn[u];
                     w1[u] = w1n[u];
                     w2[u] = w2n[u];
+                    hv[u] = hvn[u];
                 }
             }
         }
@@ -832,6 +878,7 @@ __global__ __launch_bounds__(kBlock) void line_kernel(LineArgs a, int32_t nb_chu
     o.G1 = a.G1;
     o.G2 = a.G2;
     o.H2 = a.H2;
+    o.hot = a.hot;
     o.R = OP == OP_FUSED1S ? a.values : a.out;
     o.cg_X = a.cg_X;
     o.cg_R = a.cg_R;

@@ -439,6 +439,27 @@ hipError_t gather_values(const int32_t *perm, const void *src, void *dst, int32_
     return hipGetLastError();
 }
 
+// hot[p] = 1 when minor line idx[p] has at least min_len entries (its length read from
+// the other orientation's pointer array), else 0.
+__global__ __launch_bounds__(256) void gather_hints_kernel(const int32_t *__restrict__ idx,
+                                                           const int32_t *__restrict__ minor_ptr, int32_t nnz,
+                                                           int32_t min_len, uint8_t *__restrict__ hot)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t j = idx[p];
+    hot[p] = (minor_ptr[j + 1] - minor_ptr[j]) >= min_len ? 1 : 0;
+}
+
+hipError_t gather_hints(const int32_t *idx, const int32_t *minor_ptr, int32_t nnz, int32_t min_len, uint8_t *hot,
+                        hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_hints_kernel, dim3((unsigned)(((int64_t)nnz + 255) / 256)), dim3(256), 0, s, idx,
+                       minor_ptr, nnz, min_len, hot);
+    return hipGetLastError();
+}
+
 size_t line_order_workspace_bytes(int64_t nlines)
 {
     const int64_t nb = (nlines + kSortTile - 1) / kSortTile;

@@ -32,6 +32,9 @@ __all__ = ["Pattern", "sddmm", "spmm_a", "spmm_b", "fusedmm_a", "fusedmm_b", "to
 DEFAULT_LONG_LEN = 128
 DEFAULT_CHUNK = 128
 SPLIT_CANDIDATES = (256, 128, 64)
+# Gather hints keep the rows of the longest minor lines in cache: as many rows as this
+# many bytes of gathered rows hold (the L2 of the 8 XCDs together: 32 MiB).
+HINT_BYTES = 32 << 20
 _NO_SPLIT = (1 << 31) - 1
 
 
@@ -132,6 +135,8 @@ class Pattern:
         self._csc_sched = None
         self._split = split
         self._orders = {C.FMM_CSR: None, C.FMM_CSC: None}
+        self._hints = {C.FMM_CSR: None, C.FMM_CSC: None}  # (top, per-entry uint8 tensor)
+        self._hint_cache = {}
         self._ws_cache = {}
         if validate:
             C.call("fmm_validate", ctypes.byref(self._desc(C.FMM_CSR, with_sched=False)), _stream())
@@ -226,6 +231,7 @@ class Pattern:
             raise TypeError(f"values must be {self.val_dtype} on {self.device}")
         Q = copy.copy(self)
         Q._orders = dict(self._orders)  # Q's own tuning changes must not swap tensors under self's descriptors
+        Q._hints = dict(self._hints)
         Q.val = s.detach().contiguous()
         Q.valT = torch.empty(max(1, self.nnz), dtype=self.val_dtype, device=self.device)
         vcode = C.FMM_F64 if self.val_dtype == torch.float64 else C.FMM_F32
@@ -235,6 +241,39 @@ class Pattern:
         Q.csc = Q._desc(C.FMM_CSC)
         Q.csc.variant = self.csc.variant
         return Q
+
+    def set_gather_hints(self, orient, top):
+        """Gather hints for one orientation (the library's fmm_gather_hints): entries whose
+        minor line is among the `top` longest gather their row with the default cache
+        policy, the others with the streaming policy, so the rows many entries gather stay
+        in L2 and the MALL.  top None or 0 removes the hints.  Results are unchanged."""
+        if not top:
+            self._hints[orient] = None
+        else:
+            key = (orient, int(top))
+            hot = self._hint_cache.get(key)
+            if hot is None:
+                hot = torch.empty(max(1, self.nnz), dtype=torch.uint8, device=self.device)
+                minor_ptr, n_minor = (self.colptr, self.n) if orient == C.FMM_CSR else (self.rowptr, self.m)
+                d = self._desc(orient)
+                C.call("fmm_gather_hints", ctypes.byref(d), _ptr(minor_ptr), n_minor, int(top), _ptr(hot),
+                       _stream())
+                self._hint_cache[key] = hot
+            self._hints[orient] = (int(top), hot)
+        self._refresh(orient)
+
+    def minor_skewed(self, orient):
+        """True when the minor lines of an orientation (columns for FMM_CSR, rows for
+        FMM_CSC) have hubs: the longest is over four times the mean."""
+        other = C.FMM_CSC if orient == C.FMM_CSR else C.FMM_CSR
+        nl = self.n if orient == C.FMM_CSR else self.m
+        return nl > 0 and self.max_line(other) > 4.0 * self.nnz / nl
+
+    @property
+    def gather_hints(self):
+        """Gather-hint setting of each orientation: the number of hot minor lines, or None."""
+        return {k: (self._hints[o][0] if self._hints[o] is not None else None)
+                for k, o in (("csr", C.FMM_CSR), ("csc", C.FMM_CSC))}
 
     def set_line_order(self, orient, enabled: bool):
         """Process one orientation's lines by decreasing length (True) or in index order."""
@@ -262,6 +301,8 @@ class Pattern:
             d.chunks, d.splits = sch["chunks"].data_ptr(), sch["splits"].data_ptr()
         if with_sched and self._orders.get(orient) is not None:
             d.order = self._orders[orient].data_ptr()
+        if self._hints.get(orient) is not None:
+            d.hot = self._hints[orient][1].data_ptr()
         return d
 
     def descriptor(self, orient, schedule=True):
@@ -308,11 +349,13 @@ class Pattern:
         """Batch depth class of each orientation (FMM_VARIANT_*)."""
         return {"csr": self.csr.variant, "csc": self.csc.variant}
 
-    def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES, orders=(False, True)):
+    def autotune(self, A, B, dC, form="a", split_candidates=SPLIT_CANDIDATES, orders=(False, True),
+                 hint_candidates=True):
         """Time FusedMMA (form "a") or FusedMMB ("b") forward and adjoint on these operands
         and keep, per orientation, the fastest combination of split threshold (from
-        split_candidates, where some line is longer), line order (from `orders`) and
-        batch depth.  The library's fmm_autotune picks the depth for each combination;
+        split_candidates, where some line is longer), line order (from `orders`), gather
+        hints (off, or the HINT_BYTES worth of longest minor lines, where those have hubs)
+        and batch depth.  The library's fmm_autotune picks the depth for each combination;
         the forward times the orientation the forward runs on, the two-row adjoint pass
         the other one."""
         r = A.shape[1]
@@ -358,13 +401,18 @@ class Pattern:
 
         longest = max(self.max_line(C.FMM_CSR), self.max_line(C.FMM_CSC))
         cands = [ll for ll in split_candidates if ll < longest] if self._split else []
-        combos = [(lo, ll) for lo in orders for ll in (cands or [None])]
+        # gather hints are tried where the gathered rows have hubs
+        skewed = {o: self.minor_skewed(o) for o in (C.FMM_CSR, C.FMM_CSC)}
+        top = max(1, HINT_BYTES // (r * A.element_size()))
+        hints = (None, top) if hint_candidates and any(skewed.values()) else (None,)
+        combos = [(lo, ll, h) for lo in orders for ll in (cands or [None]) for h in hints]
         best = {}
-        for lo, ll in combos:
+        for lo, ll, h in combos:
             for o in (C.FMM_CSR, C.FMM_CSC):
                 if ll is not None:
                     self.set_split(o, ll)
                 self.set_line_order(o, lo)
+                self.set_gather_hints(o, h if skewed[o] else None)
             tune_depth()
             if len(combos) == 1:
                 return self.variants
@@ -372,11 +420,12 @@ class Pattern:
                 ms = time_it(fn)
                 v = self.csr.variant if o == C.FMM_CSR else self.csc.variant
                 if o not in best or ms < best[o][0]:
-                    best[o] = (ms, lo, ll, v)
-        for o, (_, lo, ll, v) in best.items():
+                    best[o] = (ms, lo, ll, h if skewed[o] else None, v)
+        for o, (_, lo, ll, h, v) in best.items():
             if ll is not None:
                 self.set_split(o, ll)
             self.set_line_order(o, lo)
+            self.set_gather_hints(o, h)
             if o == C.FMM_CSR:
                 self.csr.variant = v
             else:
@@ -388,8 +437,9 @@ class Pattern:
         """Per orientation: batch depth, split threshold (None: no split schedule) and
         whether the line order is on."""
         sp = self.splits
+        gh = self.gather_hints
         return {k: {"variant": (self.csr if k == "csr" else self.csc).variant, "long_len": sp[k],
-                    "line_order": self.orders[k] is not None} for k in ("csr", "csc")}
+                    "line_order": self.orders[k] is not None, "gather_hints": gh[k]} for k in ("csr", "csc")}
 
     def apply_tuning(self, tuning):
         """Put back a configuration that `tuning` reported (for instance one saved as JSON
@@ -400,6 +450,7 @@ class Pattern:
             t = tuning[key]
             self.set_split(orient, t["long_len"] if t["long_len"] is not None else _NO_SPLIT)
             self.set_line_order(orient, bool(t["line_order"]))
+            self.set_gather_hints(orient, t.get("gather_hints"))
         self.set_variant(tuning["csr"]["variant"], tuning["csc"]["variant"])
 
     @property

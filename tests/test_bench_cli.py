@@ -213,3 +213,32 @@ def test_marked_summary_counts_only_the_marked_regions(tmp_path):
     assert t["regions"]["fwd_f32"]["bytes_per_step"] == int(1024 * ((10 + 30) * 2 + (1 + 3)) / 2)
     assert t["regions"]["bwd_f32"]["bytes_per_step"] == int(1024 * (7 * 2 + 5) / 2)
     assert t["regions"]["fwd_f32"]["dispatches"] == 2
+
+
+def test_tuning_arg_round_trips():
+    t = {"csr": {"variant": 3, "long_len": 256, "line_order": False, "gather_hints": 32768},
+         "csc": {"variant": 1, "long_len": None, "line_order": True, "gather_hints": None}}
+    arg = bench.tuning_arg(t)
+    assert arg == "csr=3:256:0:32768,csc=1:0:1:0"
+    assert bench.parse_tuning_arg(arg) == t
+    old = bench.parse_tuning_arg("csr=3:256:1,csc=3:256:0")  # the form without hints
+    assert old["csr"]["gather_hints"] is None and old["csr"]["line_order"] is True
+
+
+def test_trace_summary_reports_the_timed_region(tmp_path):
+    """Launches between the first two marker dispatches of a kernel trace are averaged on
+    their own, next to the statistics of the whole run."""
+    d = tmp_path / "t"
+    os.makedirs(d)
+    mk = "fmm::(anonymous namespace)::stream_read_kernel(unsigned int __vector(4) const*, unsigned long)"
+    lk = "void fmm::line_kernel<4, float, float, float, float, 64, 1, 4, 1>(fmm::LineArgs, int)"
+    rows = [(lk, 0, 30), (mk, 100, 101), (lk, 200, 210), (lk, 300, 312), (mk, 400, 401), (lk, 500, 540)]
+    with open(d / "trace_kernel_trace.csv", "w") as fh:
+        fh.write("Kind,Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for k, a, b in rows:
+            fh.write(f'KERNEL_DISPATCH,"{k}",{a * 1000},{b * 1000}\n')
+    _write_stats(str(d), [(lk, 4, 23000.0), (mk, 2, 1000.0)])
+    out = str(tmp_path / "s.md")
+    bench.trace_summary(str(d), out)
+    text = open(out).read()
+    assert "| 2 | 11.0 |" in text  # two timed launches of 10 and 12 us

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(lib, n), n
         assert n in C.SIGNATURES, n
-    assert lib.fmm_abi_version() == 3
+    assert lib.fmm_abi_version() == 4
 
 
 def test_status_strings():

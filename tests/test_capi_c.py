@@ -68,7 +68,7 @@ def test_header_is_c_and_matches_the_binding(tmp_path):
     for c in CONSTANTS:
         want = C.load().fmm_abi_version() if c == "FMM_ABI_VERSION" else getattr(C, c)
         assert int(got[("const", c)]) == want, c
-    assert int(got[("call", "abi")]) == 3
+    assert int(got[("call", "abi")]) == 4
     assert int(got[("call", "null")]) == -1
     assert int(got[("call", "orient")]) == -4   # a CSC descriptor where CSR is required
     assert got[("call", "status")] == C.status_string(-7)

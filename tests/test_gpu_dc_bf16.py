@@ -1,10 +1,10 @@
 """GPU parity of the adjoints with a bfloat16 upstream gradient (FMM_DC_BF16), against
 the FP64 oracle: within the bf16-storage gate on the original float32 A, B, dC, and
 within the float32 gate on the bf16-rounded ones (so the only extra error is the
-rounding of dC).  Results repeat bit for bit, also when one output is computed alone.
-They need not equal the float32-dC call on the rounded dC bit for bit: the compiler
-may contract the update's multiply-adds differently when an operand is widened from
-bfloat16."""
+rounding of dC).  Results repeat bit for bit, also when one output is computed alone,
+and equal the float32-dC call on the rounded dC bit for bit: every multiply-add of the
+line kernels is an explicit fused multiply-add, so widening an operand from bfloat16
+changes no rounding."""
 import pytest
 import torch
 
@@ -51,6 +51,9 @@ def test_bf16_upstream_gradient_parity(case):
         gate(f"{case} {form} dB rounded inputs", host(dB), qB, qmB, TOL_F32)
         rA, rB = raw(P, Ad, Bd, G16)
         assert torch.equal(dA, rA) and torch.equal(dB, rB)
+        # the same arithmetic as the float32-dC call on the rounded gradient
+        fA, fB = raw(P, Ad, Bd, G16.float())
+        assert torch.equal(dA, fA) and torch.equal(dB, fB)
         # one output at a time gives the same bits
         oA, _ = raw(P, Ad, Bd, G16, need=(True, False))
         _, oB = raw(P, Ad, Bd, G16, need=(False, True))

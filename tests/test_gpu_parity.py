@@ -509,3 +509,69 @@ def test_line_order_gives_identical_results():
     a2 = dev(dense_normal(1, r, 200, sigma=r ** -0.5)[0])
     Hd = dev(B)
     assert torch.equal(F.gat_forward(Po, Hd, a1, a2), F.gat_forward(Pn, Hd, a1, a2))
+
+
+def _hints_ref(S, orient, top):
+    """Gather hints by their definition, on the host: entry p is hot when its minor line
+    is as long as the top-th longest minor line (every line, for top >= the count)."""
+    if orient == C.FMM_CSR:
+        idx = np.asarray(S.colidx, np.int64)
+        lens = np.bincount(idx, minlength=S.n)
+    else:
+        ST = oracle.transpose(S)
+        idx = np.asarray(ST.colidx, np.int64)
+        lens = np.diff(np.asarray(S.rowptr, np.int64))
+    if top <= 0:
+        return np.zeros(idx.size, np.uint8)
+    if top >= lens.size:
+        return np.ones(idx.size, np.uint8)
+    thr = max(1, int(np.sort(lens)[::-1][top - 1]))
+    return (lens[idx] >= thr).astype(np.uint8)
+
+
+def test_gather_hints_exact_and_results_unchanged():
+    """fmm_gather_hints marks exactly the entries of the top minor lines (bit-exact against
+    the host definition, both orientations, with ties, none and all), and hints change
+    only cache policy: every output is bit-identical with and without them."""
+    S = rmat(11, 8, seed=205)
+    r = 64
+    A, B = _inputs(S, r, 206, torch.float32)
+    G = dense_normal(S.m, r, 207)
+    Gb = dense_normal(S.n, r, 208)
+    log("gather hints")
+    Ph = _pattern(S, long_len=64, chunk=32, line_order=True)
+    Pn = _pattern(S, long_len=64, chunk=32, line_order=True)
+    for orient in (C.FMM_CSR, C.FMM_CSC):
+        for top in (1, 37, 300, S.n + 5):
+            Ph.set_gather_hints(orient, top)
+            got = Ph._hints[orient][1][:S.nnz].cpu().numpy()
+            assert np.array_equal(got, _hints_ref(S, orient, top)), (orient, top)
+        Ph.set_gather_hints(orient, 200)
+    assert Ph.csr.hot and Ph.csc.hot and not Pn.csr.hot
+    assert Ph.gather_hints == {"csr": 200, "csc": 200}
+    for dtype in (torch.float32, torch.bfloat16):
+        Ad, Bd = _to_dev(A, dtype), _to_dev(B, dtype)
+        for fused in (True, False):
+            outs = []
+            for P in (Ph, Pn):
+                Ca, Ra = F.fusedmm_a_raw(P, Ad, Bd, fused=fused)
+                Cb, _ = F.fusedmm_b_raw(P, Ad, Bd, fused=fused)
+                gA, gB = F.fusedmm_a_backward_raw(P, Ad, Bd, dev(G), fused=fused, R_ws=None if fused else Ra)
+                hA, hB = F.fusedmm_b_backward_raw(P, Ad, Bd, dev(Gb), fused=fused,
+                                                  R_ws=None if fused else F.fusedmm_b_raw(P, Ad, Bd, fused=False)[1])
+                outs.append([Ca, Cb, gA, gB, hA, hB, F.sddmm_raw(P, Ad, Bd), F.spmm_a_raw(P, Bd),
+                             F.spmm_b_raw(P, Ad)])
+            for x, y in zip(*outs):
+                assert torch.equal(x, y)
+    # the fp64 path and the autotuner with hints
+    A64, B64 = dev(np.asarray(A, np.float64)), dev(np.asarray(B, np.float64))
+    S64 = type(S)(S.m, S.n, S.rowptr, S.colidx, np.asarray(S.val, np.float64))
+    P64 = F.Pattern.from_csr(S64, long_len=64, chunk=32)
+    want, _ = F.fusedmm_a_raw(P64, A64, B64)
+    P64.set_gather_hints(C.FMM_CSR, 100)
+    assert torch.equal(F.fusedmm_a_raw(P64, A64, B64)[0], want)
+    Pn.autotune(_to_dev(A, torch.float32), _to_dev(B, torch.float32), dev(G), form="a")
+    assert set(Pn.tuning["csr"]) == {"variant", "long_len", "line_order", "gather_hints"}
+    ref, mag = ref_fusedmm_a(S, A, B)
+    gate("autotuned with hints", host(F.fusedmm_a_raw(Pn, _to_dev(A, torch.float32), _to_dev(B, torch.float32))[0]),
+         ref, mag, TOL_F32)
