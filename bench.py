@@ -1226,6 +1226,10 @@ def main():
                 "kernel_ms": round(kt[dom], 4), "bytes_per_launch": int(dom_bytes),
                 "bytes_model": "gather (each stored entry fetches its dense row(s))",
                 "frac_gather_model": round(achieved / HBM_PEAK_GBS, 4),
+                "frac_note": "frac counts every gathered row as moved (the gather model); rows served from L2 or "
+                             "the MALL let it pass 1, as on R-MAT, where hub rows are gathered many times. "
+                             "frac_counters uses the counted L2-to-fabric bytes, frac_compulsory_bytes every "
+                             "array once.",
                 "frac_compulsory_bytes": round(kernel_bytes_min(dom, m, n, nnz, r, e) / (kt[dom] * 1e-3) / 1e9
                                                / HBM_PEAK_GBS, 4),
                 "bytes_compulsory": int(kernel_bytes_min(dom, m, n, nnz, r, e)),

@@ -234,6 +234,9 @@ fmm_status apply_schedule(fmm_batch_plan *p, int32_t tile_nnz, int32_t placement
     if (placement == FMM_BATCH_PLACE_QUEUES) queue_tiles(p, per_graph, &tiles, &off);
     else place_tiles(p, per_graph, n_wg, placement == FMM_BATCH_PLACE_XCD, &tiles, &off);
     release_graph(p);
+    // queue counters start from zero under every new schedule (each launch also leaves them
+    // at zero; this also recovers from a launch that did not run to its end)
+    BTRY(hipMemset(p->qnext_dev, 0, sizeof(int32_t) * (p->n_xcd + 1)));
     if (p->tiles_dev) BTRY(hipFree(p->tiles_dev));
     if (p->wgoff_dev) BTRY(hipFree(p->wgoff_dev));
     p->tiles_dev = nullptr;
