@@ -18,13 +18,13 @@ from tests.gpu_helpers import dev, gate, host, log
 from workloads import workload
 
 # Configurations the benchmark's autotuner chose for R-MAT scale 22, r = 256 on MI355X
-# (batch depth class, split threshold, line order per orientation), for float32 and for
-# bfloat16 storage.  The adjoint test runs under these and under the autotuner's own pick.
+# (batch depth class, split threshold, line order and gather hints per orientation), for
+# float32 and for bfloat16 storage.  The adjoint test runs under these and under the autotuner's own pick.
 RMAT22_BENCH_TUNING = {
-    "f32": {"csr": {"variant": 3, "long_len": 256, "line_order": False},
-            "csc": {"variant": 3, "long_len": 256, "line_order": False}},
-    "bf16": {"csr": {"variant": 3, "long_len": 256, "line_order": True},
-             "csc": {"variant": 3, "long_len": 256, "line_order": False}},
+    "f32": {"csr": {"variant": 2, "long_len": 256, "line_order": False, "gather_hints": 32768},
+            "csc": {"variant": 3, "long_len": 256, "line_order": False, "gather_hints": 32768}},
+    "bf16": {"csr": {"variant": 3, "long_len": 256, "line_order": True, "gather_hints": None},
+             "csc": {"variant": 2, "long_len": 256, "line_order": False, "gather_hints": 65536}},
 }
 
 pytestmark = pytest.mark.gpu
