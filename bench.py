@@ -894,6 +894,56 @@ def calibrate_copy(dev):
 PROBE_BYTES = 4 << 30  # long enough for the streaming probes to reach their full rate
 
 
+def median_event_ms(fn, reps):
+    """Median over `reps` calls of fn (after two untimed ones) of its HIP-event time on the
+    current stream."""
+    import torch
+
+    for _ in range(2):
+        fn()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms))
+
+
+# working sets of the gather ceilings: the whole probe buffer (rows come from HBM), 192 MiB
+# (held by the 256 MB MALL but by no L2) and 2 MiB (held by every XCD's 4 MB L2)
+GATHER_SETS = (("hbm_random", PROBE_BYTES), ("mall_resident", 192 << 20), ("l2_resident", 2 << 20))
+
+
+def gather_ceiling(dev, row_bytes, reps=5):
+    """Measured ceilings of random row gathers with the library's gather probe (one 16-byte
+    load per lane, as the line kernels gather rows): PROBE_BYTES worth of rows of row_bytes
+    bytes per launch, drawn uniformly (seeded) from each working set of GATHER_SETS.  Rate =
+    rows x (row bytes + 4 index bytes) / median event time."""
+    import torch
+
+    import paper_2203_07673_amd as F
+    from paper_2203_07673_amd import _capi as CA
+
+    src = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(13)
+    n = PROBE_BYTES // row_bytes
+    out = {"row_bytes": row_bytes, "rows_per_launch": n, "kernel": "fmm_stream_gather (gather_rows_kernel)"}
+    for name, ws in GATHER_SETS:
+        rows = torch.randint(0, ws // row_bytes, (n,), generator=gen, device=dev, dtype=torch.int32)
+        F.stream_gather(src, row_bytes, rows, sink)  # checks every index once; the timed calls go straight in
+        stream = torch.cuda.current_stream().cuda_stream
+        t = median_event_ms(lambda: CA.call("fmm_stream_gather", src.data_ptr(), row_bytes, rows.data_ptr(), n,
+                                            0x9E3779B9, sink.data_ptr(), stream), reps)
+        out[f"{name}_gbs"] = round(n * (row_bytes + 4) / (t * 1e-3) / 1e9, 1)
+        del rows
+    return out
+
+
 def copy_ceiling(dev, reps=10):
     """Measured HBM ceilings on contiguous traffic: the library's read-only pass over
     PROBE_BYTES and its plain copy of PROBE_BYTES / 2 (read + write, PROBE_BYTES moved),
@@ -906,19 +956,7 @@ def copy_ceiling(dev, reps=10):
     half = src[:PROBE_BYTES // 8]
     dst = torch.empty_like(half)
     sink = torch.zeros(1, dtype=torch.int32, device=dev)
-
-    def median_ms(fn):
-        for _ in range(2):
-            fn()
-        ms = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        return float(np.median(ms))
+    median_ms = lambda fn: median_event_ms(fn, reps)  # noqa: E731
 
     t_copy = median_ms(lambda: F.stream_copy(half, dst))
     t_read = median_ms(lambda: F.stream_read(src, sink))
@@ -1352,6 +1390,15 @@ def main():
         log(f"ceilings: copy {ceiling['gbs']:.0f} GB/s, read {ceiling['read_gbs']:.0f} GB/s, torch copy "
             f"{ceiling['torch_copy_gbs']:.0f} GB/s; dominant kernel at {achieved / ceiling['gbs']:.3f} / "
             f"{achieved / ceiling['read_gbs']:.3f} of them")
+        # random-gather ceilings at the dominant kernel's gathered row size: what the L2-miss
+        # path sustains for rows from HBM and for rows held by the MALL
+        gc = gather_ceiling(dev, 1 << (min(1024, r * e).bit_length() - 1))  # the probe takes 16·2^k bytes
+        roofline["gather_ceiling"] = gc
+        if traffic is not None:
+            rate = traffic / (kt[dom] * 1e-3) / 1e9
+            roofline["frac_counters_of_gather_ceiling"] = round(rate / gc["mall_resident_gbs"], 4)
+        log(f"gather ceilings ({gc['row_bytes']} B rows): HBM random {gc['hbm_random_gbs']:.0f} GB/s, "
+            f"MALL-resident {gc['mall_resident_gbs']:.0f} GB/s, L2-resident {gc['l2_resident_gbs']:.0f} GB/s")
         variants["pattern_prep_s"] = round(prep_s, 3)
         variants["step_bytes_gather_model"] = int(step_bytes)
         variants["step_hbm_frac_gather_model"] = round(step_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)
