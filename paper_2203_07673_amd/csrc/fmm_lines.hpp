@@ -44,6 +44,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 
 namespace fmm {
 
@@ -95,6 +97,21 @@ struct LineArgs {
 
 __device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+// Two floats that are bfloat16 values (widened exactly) packed back into one word, lo first.
+__device__ __forceinline__ uint32_t bf16_pack_exact(float lo, float hi)
+{
+    return (__float_as_uint(hi) & 0xffff0000u) | (__float_as_uint(lo) >> 16);
+}
+
+// c + a.lo * b.lo + a.hi * b.hi over two packed bfloat16 pairs: gfx950's bf16 dot
+// instruction (v_dot2c_f32_bf16).  Each product of two bfloat16 values is exact in
+// float32, so only the accumulation rounds; it replaces two widenings of b and two FMAs.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
+                                           false);
+}
 
 // Streaming (nontemporal) cache hint for data a pass touches once, so that it does not
 // displace gathered rows (the only reused data) from L2 and the MALL.  On by default for
@@ -315,8 +332,9 @@ template <> struct Raw<bf16_t, 8> {
     // Make the packed words opaque to the optimiser, so elements widened for the dot
     // product are widened again for the update instead of staying live in between.
     __device__ __forceinline__ void pin() { asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w)); }
+    __device__ __forceinline__ uint32_t word(int k) const { return k == 0 ? x.x : k == 1 ? x.y : k == 2 ? x.z : x.w; }
     __device__ __forceinline__ float get(int e) const {
-        const uint32_t w = (e >> 1) == 0 ? x.x : (e >> 1) == 1 ? x.y : (e >> 1) == 2 ? x.z : x.w;
+        const uint32_t w = word(e >> 1);
         return (e & 1) ? bf16_hi(w) : bf16_lo(w);
     }
 };
@@ -582,6 +600,27 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
         }
     }
 
+    // A dot product of two bfloat16 vectors takes the bf16 dot instruction on packed words
+    // (dot2_bf16), so the held rows it uses are kept packed as well; packing the widened
+    // values back is exact.  Dot products with a float32 operand stay FMA chains.
+    constexpr bool kF32 = std::is_same<Acc, float>::value && VW == 8;
+    constexpr bool kDotH = kF32 && std::is_same<TH, bf16_t>::value && std::is_same<TG1, bf16_t>::value;  // <H, G1>
+    constexpr bool kDotHG2 = kF32 && OP == OP_FUSED2 && std::is_same<TH, bf16_t>::value &&
+                             std::is_same<TG2, bf16_t>::value;                                             // <H, G2>
+    constexpr bool kDotH2 = kF32 && kHeld2 && std::is_same<TG2, bf16_t>::value &&
+                            std::is_same<TG1, bf16_t>::value;                                              // <H2, G1>
+    constexpr int PW = VW / 2;  // packed words per vector
+    uint32_t hp[(kDotH || kDotHG2) ? NV * PW : 1];
+    if constexpr (kDotH || kDotHG2) {
+#pragma unroll
+        for (int k = 0; k < NV * PW; ++k) hp[k] = bf16_pack_exact(h[2 * k], h[2 * k + 1]);
+    }
+    uint32_t h2p[kDotH2 ? NV * PW : 1];
+    if constexpr (kDotH2) {
+#pragma unroll
+        for (int k = 0; k < NV * PW; ++k) h2p[k] = bf16_pack_exact(h2[2 * k], h2[2 * k + 1]);
+    }
+
     Acc acc[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = Acc(0);
@@ -693,12 +732,22 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
             for (int u = 0; u < U; ++u) {
                 Acc s1 = Acc(0), s2 = Acc(0);
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
+                for (int v = 0; v < NV; ++v) {
+                    if constexpr (kDotHG2) {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        s1 = fmadd(h[v * VW + e], Acc(g2[u][v].get(e)), s1);
-                        s2 = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s2);
+                        for (int k = 0; k < PW; ++k) s1 = dot2_bf16(hp[v * PW + k], g2[u][v].word(k), s1);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) s1 = fmadd(h[v * VW + e], Acc(g2[u][v].get(e)), s1);
                     }
+                    if constexpr (kDotH) {
+#pragma unroll
+                        for (int k = 0; k < PW; ++k) s2 = dot2_bf16(hp[v * PW + k], g1[u][v].word(k), s2);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) s2 = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s2);
+                    }
+                }
                 d1[u] = s1;
                 d2[u] = s2;
             }
@@ -731,12 +780,22 @@ __device__ __forceinline__ void process_line(const LineOperands &o, int lane, in
             for (int u = 0; u < U; ++u) {
                 Acc s = Acc(0), s2 = Acc(0);
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
+                for (int v = 0; v < NV; ++v) {
+                    if constexpr (kDotH) {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        s = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s);
-                        if constexpr (kHeld2) s2 = fmadd(h2[v * VW + e], Acc(g1[u][v].get(e)), s2);
+                        for (int k = 0; k < PW; ++k) s = dot2_bf16(hp[v * PW + k], g1[u][v].word(k), s);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) s = fmadd(h[v * VW + e], Acc(g1[u][v].get(e)), s);
                     }
+                    if constexpr (kDotH2) {
+#pragma unroll
+                        for (int k = 0; k < PW; ++k) s2 = dot2_bf16(h2p[v * PW + k], g1[u][v].word(k), s2);
+                    } else if constexpr (kHeld2) {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) s2 = fmadd(h2[v * VW + e], Acc(g1[u][v].get(e)), s2);
+                    }
+                }
                 d[u] = s;
                 if constexpr (kHeld2) dv[u] = s2;
             }
