@@ -473,6 +473,76 @@ def load_traffic(workload_name, kernel_key):
     return (k["FETCH_SIZE"] * sf + k["WRITE_SIZE"] * sw) * 1024.0
 
 
+# Instruction-issue counters, one rocprofv3 --pmc pass (8 SQ counters, the most one pass holds).
+SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_BUSY_CU_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU_FMA_F32",
+               "SQ_INSTS_VMEM_RD", "SQ_INSTS_FLAT", "SQ_INSTS_SALU", "SQ_WAVES")
+SQ_FILE = "sq_issue.json"
+
+
+def sq_summary(out_md, runs, command="", tuned=""):
+    """VALU issue use per hot-path kernel from one --pmc pass of SQ_COUNTERS per run
+    (NAME=DIR).  A CU has 4 SIMDs of 16 lanes and a wave64 VALU instruction takes 4 cycles on
+    one, so a CU issues at most one VALU wave-instruction per cycle: VALU issue use =
+    SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES (both summed over the CUs).  Writes OUT_MD and, beside
+    it, profiles' SQ_FILE with the same figures for the bench lines."""
+    table = {}
+    for spec in runs:
+        name, d = spec.split("=", 1)
+        per = {}
+        for row in _csv_rows(d, "counter_collection.csv"):
+            if row.get("Counter_Name") in SQ_COUNTERS:
+                key = _short_kernel(row["Kernel_Name"])
+                if _role(key) is None:
+                    continue
+                did = int(row["Dispatch_Id"])
+                per.setdefault(key, {}).setdefault(did, {})
+                per[key][did][row["Counter_Name"]] = per[key][did].get(row["Counter_Name"], 0.0) + \
+                    float(row["Counter_Value"])
+        kern = {}
+        for key, ds in per.items():
+            mean = {c: sum(v.get(c, 0.0) for v in ds.values()) / len(ds) for c in SQ_COUNTERS}
+            busy = mean["SQ_BUSY_CU_CYCLES"]
+            kern[key] = {"dispatches": len(ds), **{c: mean[c] for c in SQ_COUNTERS},
+                         "valu_issue_frac": mean["SQ_INSTS_VALU"] / busy if busy > 0 else None,
+                         "fma_share_of_valu": mean["SQ_INSTS_VALU_FMA_F32"] / mean["SQ_INSTS_VALU"]
+                         if mean["SQ_INSTS_VALU"] > 0 else None}
+        table[name] = kern
+    lines = ["# VALU issue use of the hot-path kernels (SQ counters)", "", f"Command: `{command}`", "",
+             "A CU has 4 SIMDs of 16 lanes; a wave64 VALU instruction occupies one SIMD for 4 cycles, so a CU "
+             "issues at most one VALU wave-instruction per cycle. VALU issue use = SQ_INSTS_VALU / "
+             "SQ_BUSY_CU_CYCLES (both summed over the CUs, per dispatch). FMA share = SQ_INSTS_VALU_FMA_F32 / "
+             "SQ_INSTS_VALU: the part of the issued VALU work that is the method's own multiply-adds.", ""]
+    for name, kern in table.items():
+        lines += [f"## {name}", "", "| kernel | role | dispatches | VALU wave-instr | VMEM rd | FLAT | SALU | "
+                  "busy CU-cycles | VALU issue use | FMA share |", "|---|---|---|---|---|---|---|---|---|---|"]
+        for key, k in sorted(kern.items(), key=lambda kv: -kv[1]["SQ_BUSY_CU_CYCLES"]):
+            lines.append(f"| `{key}` | {_role(key)} | {k['dispatches']} | {k['SQ_INSTS_VALU']:.4g} | "
+                         f"{k['SQ_INSTS_VMEM_RD']:.4g} | {k['SQ_INSTS_FLAT']:.4g} | {k['SQ_INSTS_SALU']:.4g} | "
+                         f"{k['SQ_BUSY_CU_CYCLES']:.4g} | {k['valu_issue_frac']:.3f} | {k['fma_share_of_valu']:.3f} |")
+        lines.append("")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    with open(os.path.join(os.path.dirname(os.path.abspath(out_md)), SQ_FILE), "w") as fh:
+        json.dump({"command": command, "source_hash": source_hash(BATCH_SRC_GLOBS), "tuned": tuned, "runs": table},
+                  fh, indent=1)
+    print("\n".join(lines))
+    return table
+
+
+def load_valu_issue(run, kernel_prefix):
+    """VALU issue use of a kernel in a run of the committed SQ summary, while the line-kernel
+    and batch sources hash as they did when it was taken (else None)."""
+    f = os.path.join(ROOT, "profiles", SQ_FILE)
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash(BATCH_SRC_GLOBS):
+        return None
+    k = next((v for kk, v in t.get("runs", {}).get(run, {}).items() if kk.startswith(kernel_prefix)), None)
+    return None if k is None else k.get("valu_issue_frac")
+
+
 MARKER_KERNEL = "stream_read_kernel"
 # sources of the application passes (their counter data go stale when these change)
 APP_SRC_GLOBS = {"gat_rmat20_r128_h4": SRC_GLOBS + ("paper_2203_07673_amd/csrc/gat*.hip",),
@@ -680,7 +750,9 @@ def run_batch(args):
                      "bytes_model": "compulsory: every array of every graph once per launch (rows gathered "
                                     "again hit in L2, so the gather model is no bound here)",
                      "bytes_gather_model": int(bytes_launch),
-                     "frac_gather_model": round(bytes_launch / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "frac_gather_model": round(bytes_launch / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     # share of the CUs' VALU issue slots the kernel used (committed SQ counters)
+                     "valu_issue_frac": load_valu_issue("batch256_r64", kernel_key)},
         "variants": variants,
     }
     if args.calibrate_copy:
@@ -1100,6 +1172,8 @@ def main():
                     help="run only the gather probes of known size and the plain copies (for a --pmc run)")
     ap.add_argument("--gather-summary", nargs=2, metavar=("FETCH_DIR", "OUT_MD"),
                     help="summarise a FETCH_SIZE run of --calibrate-gather and exit")
+    ap.add_argument("--sq-summary", nargs="+", metavar="OUT_MD NAME=DIR",
+                    help="VALU issue use per hot-path kernel from --pmc runs of SQ_COUNTERS, and exit")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -1110,6 +1184,9 @@ def main():
         return
     if args.counter_table:
         counter_table(args.counter_table[0], args.counter_table[1:], command=args.command)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary[0], args.sq_summary[1:], command=args.command, tuned=args.tuned)
         return
     if args.gather_summary:
         gather_summary(*args.gather_summary, command=args.command)
@@ -1275,7 +1352,9 @@ def main():
                 round(traffic / (kt[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "step_traffic": None if step_traffic is None else int(step_traffic),
                 "step_traffic_frac": None if step_traffic is None else
-                round(step_traffic / (sum(kt.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                round(step_traffic / (sum(kt.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                # share of the CUs' VALU issue slots the kernel used (committed SQ counters)
+                "valu_issue_frac": load_valu_issue(args.workload, kernel_key)}
 
     variants = {}
     if not args.no_variants:

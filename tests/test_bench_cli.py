@@ -242,3 +242,34 @@ def test_trace_summary_reports_the_timed_region(tmp_path):
     bench.trace_summary(str(d), out)
     text = open(out).read()
     assert "| 2 | 11.0 |" in text  # two timed launches of 10 and 12 us
+
+
+def test_sq_summary_reports_valu_issue_use(tmp_path, monkeypatch):
+    """VALU issue use = VALU wave-instructions over busy CU-cycles, per hot-path kernel and
+    run; the bench lines read it back while the sources match."""
+    lk = "void fmm::line_kernel<4, float, float, float, float, 64, 1, 4, 1>(fmm::LineArgs, int)"
+    other = "some_torch_kernel"
+    d = tmp_path / "run"
+    os.makedirs(d)
+    vals = {"SQ_INSTS_VALU": 300.0, "SQ_BUSY_CU_CYCLES": 1000.0, "SQ_ACTIVE_INST_VALU": 310.0,
+            "SQ_INSTS_VALU_FMA_F32": 150.0, "SQ_INSTS_VMEM_RD": 40.0, "SQ_INSTS_FLAT": 10.0,
+            "SQ_INSTS_SALU": 20.0, "SQ_WAVES": 8.0}
+    with open(d / "pmc_counter_collection.csv", "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i in (1, 2):  # two dispatches of the line kernel, the second twice as long
+            for c, v in vals.items():
+                fh.write(f'{i},"{lk}",{c},{v * i}\n')
+        for c, v in vals.items():  # not a hot-path kernel: left out
+            fh.write(f'3,"{other}",{c},{v}\n')
+    prof = tmp_path / "profiles"
+    os.makedirs(prof)
+    table = bench.sq_summary(str(prof / "sq_issue.md"), [f"rmat22_ef16_r256={d}"], command="rocprofv3 test")
+    k = table["rmat22_ef16_r256"]["line_kernel<4, float, float, float, float, 64, 1, 4, 1>"]
+    assert k["dispatches"] == 2 and abs(k["valu_issue_frac"] - 0.3) < 1e-12 and abs(k["fma_share_of_valu"] - 0.5) < 1e-12
+    assert len(table["rmat22_ef16_r256"]) == 1
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda globs=None: json.load(open(prof / "sq_issue.json"))["source_hash"])
+    assert abs(bench.load_valu_issue("rmat22_ef16_r256", "line_kernel<4, float") - 0.3) < 1e-12
+    assert bench.load_valu_issue("batch256_r64", "void fmm::batch_queue_kernel") is None
+    monkeypatch.setattr(bench, "source_hash", lambda globs=None: "another")
+    assert bench.load_valu_issue("rmat22_ef16_r256", "line_kernel<4, float") is None
