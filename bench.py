@@ -479,7 +479,7 @@ SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_BUSY_CU_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_
 SQ_FILE = "sq_issue.json"
 
 
-def sq_summary(out_md, runs, command="", tuned=""):
+def sq_summary(out_md, runs, command=""):
     """VALU issue use per hot-path kernel from one --pmc pass of SQ_COUNTERS per run
     (NAME=DIR).  A CU has 4 SIMDs of 16 lanes and a wave64 VALU instruction takes 4 cycles on
     one, so a CU issues at most one VALU wave-instruction per cycle: VALU issue use =
@@ -506,13 +506,14 @@ def sq_summary(out_md, runs, command="", tuned=""):
                          "valu_issue_frac": mean["SQ_INSTS_VALU"] / busy if busy > 0 else None,
                          "fma_share_of_valu": mean["SQ_INSTS_VALU_FMA_F32"] / mean["SQ_INSTS_VALU"]
                          if mean["SQ_INSTS_VALU"] > 0 else None}
-        table[name] = kern
+        table[name] = {"source_hash": source_hash(source_globs(name)), "kernels": kern}
     lines = ["# VALU issue use of the hot-path kernels (SQ counters)", "", f"Command: `{command}`", "",
              "A CU has 4 SIMDs of 16 lanes; a wave64 VALU instruction occupies one SIMD for 4 cycles, so a CU "
              "issues at most one VALU wave-instruction per cycle. VALU issue use = SQ_INSTS_VALU / "
              "SQ_BUSY_CU_CYCLES (both summed over the CUs, per dispatch). FMA share = SQ_INSTS_VALU_FMA_F32 / "
              "SQ_INSTS_VALU: the part of the issued VALU work that is the method's own multiply-adds.", ""]
-    for name, kern in table.items():
+    for name, run in table.items():
+        kern = run["kernels"]
         lines += [f"## {name}", "", "| kernel | role | dispatches | VALU wave-instr | VMEM rd | FLAT | SALU | "
                   "busy CU-cycles | VALU issue use | FMA share |", "|---|---|---|---|---|---|---|---|---|---|"]
         for key, k in sorted(kern.items(), key=lambda kv: -kv[1]["SQ_BUSY_CU_CYCLES"]):
@@ -523,23 +524,23 @@ def sq_summary(out_md, runs, command="", tuned=""):
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines))
     with open(os.path.join(os.path.dirname(os.path.abspath(out_md)), SQ_FILE), "w") as fh:
-        json.dump({"command": command, "source_hash": source_hash(BATCH_SRC_GLOBS), "tuned": tuned, "runs": table},
-                  fh, indent=1)
+        json.dump({"command": command, "runs": table}, fh, indent=1)
     print("\n".join(lines))
     return table
 
 
 def load_valu_issue(run, kernel_prefix):
-    """VALU issue use of a kernel in a run of the committed SQ summary, while the line-kernel
-    and batch sources hash as they did when it was taken (else None)."""
+    """VALU issue use of a kernel in a run of the committed SQ summary, while the sources of
+    that run's kernels hash as they did when it was taken (else None)."""
     f = os.path.join(ROOT, "profiles", SQ_FILE)
     if not os.path.exists(f):
         return None
     with open(f) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != source_hash(BATCH_SRC_GLOBS):
+    entry = t.get("runs", {}).get(run)
+    if not entry or entry.get("source_hash") != source_hash(source_globs(run)):
         return None
-    k = next((v for kk, v in t.get("runs", {}).get(run, {}).items() if kk.startswith(kernel_prefix)), None)
+    k = next((v for kk, v in entry["kernels"].items() if kk.startswith(kernel_prefix)), None)
     return None if k is None else k.get("valu_issue_frac")
 
 
@@ -1186,7 +1187,7 @@ def main():
         counter_table(args.counter_table[0], args.counter_table[1:], command=args.command)
         return
     if args.sq_summary:
-        sq_summary(args.sq_summary[0], args.sq_summary[1:], command=args.command, tuned=args.tuned)
+        sq_summary(args.sq_summary[0], args.sq_summary[1:], command=args.command)
         return
     if args.gather_summary:
         gather_summary(*args.gather_summary, command=args.command)

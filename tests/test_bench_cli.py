@@ -264,11 +264,14 @@ def test_sq_summary_reports_valu_issue_use(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     os.makedirs(prof)
     table = bench.sq_summary(str(prof / "sq_issue.md"), [f"rmat22_ef16_r256={d}"], command="rocprofv3 test")
-    k = table["rmat22_ef16_r256"]["line_kernel<4, float, float, float, float, 64, 1, 4, 1>"]
+    k = table["rmat22_ef16_r256"]["kernels"]["line_kernel<4, float, float, float, float, 64, 1, 4, 1>"]
     assert k["dispatches"] == 2 and abs(k["valu_issue_frac"] - 0.3) < 1e-12 and abs(k["fma_share_of_valu"] - 0.5) < 1e-12
-    assert len(table["rmat22_ef16_r256"]) == 1
+    assert len(table["rmat22_ef16_r256"]["kernels"]) == 1
+    # the run is keyed to the line-kernel sources (a batch-only change leaves it valid)
+    assert table["rmat22_ef16_r256"]["source_hash"] == bench.source_hash(bench.SRC_GLOBS)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "source_hash", lambda globs=None: json.load(open(prof / "sq_issue.json"))["source_hash"])
+    stored = json.load(open(prof / "sq_issue.json"))["runs"]["rmat22_ef16_r256"]["source_hash"]
+    monkeypatch.setattr(bench, "source_hash", lambda globs=None: stored)
     assert abs(bench.load_valu_issue("rmat22_ef16_r256", "line_kernel<4, float") - 0.3) < 1e-12
     assert bench.load_valu_issue("batch256_r64", "void fmm::batch_queue_kernel") is None
     monkeypatch.setattr(bench, "source_hash", lambda globs=None: "another")
