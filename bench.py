@@ -541,7 +541,8 @@ def load_valu_issue(run, kernel_prefix):
     if not entry or entry.get("source_hash") != source_hash(source_globs(run)):
         return None
     k = next((v for kk, v in entry["kernels"].items() if kk.startswith(kernel_prefix)), None)
-    return None if k is None else k.get("valu_issue_frac")
+    v = None if k is None else k.get("valu_issue_frac")
+    return None if v is None else round(v, 4)
 
 
 MARKER_KERNEL = "stream_read_kernel"
