@@ -209,3 +209,41 @@ def test_batch256_autotuned_plan_at_full_size():
         gate(f"batch256 graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
         ref, mag = ref_fusedmm_a(S, g["A"], g["B"])
         gate(f"batch256 graph {k} C vs float32 inputs", host(plan.C[k]), ref, mag, TOL_BF16)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_batch_patterns_without_values(dtype):
+    """Graphs whose pattern stores no values (every weight 1) mixed with valued ones: with
+    tiles whose operands are staged in LDS (2048 entries) and tiles that are not (8192), the
+    row-block schedule equals the single-graph calls bit for bit, and the oracle with unit
+    weights holds at the float32 gate."""
+    from workloads import CsrPattern
+    graphs, _, A, B, G = _setup(dtype, nbatch=6, seed=97)
+    pats = []
+    for k, g in enumerate(graphs):
+        S = g["S"]
+        if k % 2 == 0:  # drop the values: the pattern alone
+            pats.append(F.Pattern(S.rowptr, S.colidx, None, (S.m, S.n)))
+            g["S"] = CsrPattern(S.m, S.n, S.rowptr, S.colidx, np.ones(S.nnz, dtype=np.float32))
+        else:
+            pats.append(F.Pattern.from_csr(S))
+    plan = F.BatchPlan(pats, A, B, G)
+    single = _single(pats, A, B, G)
+    for tile in (2048, 8192):
+        log(f"batch without values dtype={dtype} tile={tile}")
+        plan.set_schedule(tile_nnz=tile, placement=F.BatchPlan.PLACE_QUEUES, row_wave=False, col_wave=False)
+        for t in plan.C + plan.dA + plan.dB:
+            t.fill_(float("nan"))
+        plan.run()
+        torch.cuda.synchronize()
+        for k, (c, da, db) in enumerate(single):
+            assert torch.equal(plan.C[k], c) and torch.equal(plan.dA[k], da) and torch.equal(plan.dB[k], db), (k, tile)
+    for k, g in enumerate(graphs):
+        S, Aq, Bq = g["S"], g["A"], g["B"]
+        if dtype == torch.bfloat16:
+            Aq, Bq = oracle.bf16_round(Aq), oracle.bf16_round(Bq)
+        ref, mag = ref_fusedmm_a(S, Aq, Bq)
+        gate(f"no-values graph {k} C", host(plan.C[k]), ref, mag, TOL_F32)
+        dA, dB, mA, mB = ref_fusedmm_a_backward(S, Aq, Bq, g["G"])
+        gate(f"no-values graph {k} dA", host(plan.dA[k]), dA, mA, TOL_F32)
+        gate(f"no-values graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
