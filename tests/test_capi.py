@@ -250,6 +250,14 @@ def test_stream_probe_argument_errors():
     assert lib.fmm_stream_read(FAKE, 64, 0, None, None) == -1
     assert lib.fmm_stream_read(FAKE, 24, 0, FAKE, None) == -2
     assert lib.fmm_stream_read(FAKE + 8, 64, 0, FAKE, None) == -8
+    assert lib.fmm_stream_gather(FAKE, 64, FAKE, 0, 0, FAKE, None) == 0          # no rows
+    assert lib.fmm_stream_gather(None, 64, FAKE, 4, 0, FAKE, None) == -1
+    assert lib.fmm_stream_gather(FAKE, 64, None, 4, 0, FAKE, None) == -1
+    assert lib.fmm_stream_gather(FAKE, 64, FAKE, 4, 0, None, None) == -1
+    assert lib.fmm_stream_gather(FAKE, 64, FAKE, -4, 0, FAKE, None) == -2
+    assert lib.fmm_stream_gather(FAKE + 8, 64, FAKE, 4, 0, FAKE, None) == -8    # misaligned
+    for rb in (0, 8, 48, 2048):  # rows of 16 * 2^k bytes, k <= 6
+        assert lib.fmm_stream_gather(FAKE, rb, FAKE, 4, 0, FAKE, None) == -2, rb
 
 
 def test_caller_buffers_are_checked():

@@ -1,7 +1,8 @@
 """The streaming probes the bench reads its HBM ceilings from: the copy is byte-exact
 (including lengths that leave a partial batch of vectors) and the read pass reads every
 word: with one nonzero word in a zero buffer, exactly one lane folds to that word, so
-the sink is written with it exactly when the key names it."""
+the sink is written with it exactly when the key names it.  The gather probe reads every
+word of exactly the listed rows, the same way."""
 import numpy as np
 import pytest
 import torch
@@ -37,6 +38,31 @@ def test_stream_read_reaches_every_position(nwords):
         assert int(sink.item()) == 0
         F.stream_read(buf, sink, key=marker)          # the lane that read buf[pos] does
         assert int(sink.item()) == marker, pos
+
+
+@pytest.mark.parametrize("row_bytes", [16, 128, 1024])
+def test_stream_gather_reads_the_listed_rows(row_bytes):
+    """A marker word in one row of a zero buffer reaches the sink exactly when that row is
+    gathered and the key names the marker; every word position of the row is tried."""
+    log(f"stream gather row_bytes={row_bytes}")
+    marker = 0x2545F491
+    nrows = 1000
+    words = row_bytes // 4
+    rng = np.random.default_rng(row_bytes)
+    listed = torch.from_numpy(rng.choice(nrows, size=300, replace=False).astype(np.int32)).cuda()
+    absent = int(np.setdiff1d(np.arange(nrows), listed.cpu().numpy())[0])
+    present = int(listed[17])
+    for row, want in ((present, marker), (absent, 0)):
+        for w in sorted({0, words // 2, words - 1}):
+            buf = torch.zeros(nrows * words, dtype=torch.int32, device="cuda")
+            buf[row * words + w] = marker
+            sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+            F.stream_gather(buf, row_bytes, listed, sink, key=marker + 1)  # no lane folds to this
+            assert int(sink.item()) == 0
+            F.stream_gather(buf, row_bytes, listed, sink, key=marker)
+            assert int(sink.item()) == want, (row, w)
+    with pytest.raises(ValueError):  # every index is checked against the buffer's rows first
+        F.stream_gather(buf, row_bytes, torch.tensor([nrows], dtype=torch.int32, device="cuda"), sink)
 
 
 def test_stream_probe_errors():
