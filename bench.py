@@ -757,6 +757,16 @@ def run_batch(args):
                      "valu_issue_frac": load_valu_issue("batch256_r64", kernel_key)},
         "variants": variants,
     }
+    if not args.no_variants:
+        # random-gather ceilings at the batch's row size (64 bf16 = 128 B): the queue kernel's
+        # L2 misses are gathers of such rows, mostly of the graphs the XCDs are working on
+        gc = gather_ceiling(dev, 2 * r)
+        out["roofline"]["gather_ceiling"] = gc
+        if traffic is not None:
+            out["roofline"]["frac_counters_of_gather_ceiling"] = round(
+                traffic / (k_ms * 1e-3) / 1e9 / gc["mall_resident_gbs"], 4)
+        log(f"gather ceilings ({gc['row_bytes']} B rows): HBM random {gc['hbm_random_gbs']:.0f} GB/s, "
+            f"MALL-resident {gc['mall_resident_gbs']:.0f} GB/s, L2-resident {gc['l2_resident_gbs']:.0f} GB/s")
     if args.calibrate_copy:
         calibrate_copy(dev)
     print(json.dumps(out), flush=True)
