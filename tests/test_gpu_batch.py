@@ -247,3 +247,41 @@ def test_batch_patterns_without_values(dtype):
         dA, dB, mA, mB = ref_fusedmm_a_backward(S, Aq, Bq, g["G"])
         gate(f"no-values graph {k} dA", host(plan.dA[k]), dA, mA, TOL_F32)
         gate(f"no-values graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
+
+
+@pytest.mark.parametrize("dtype,r", [(torch.float32, 4), (torch.float32, 256), (torch.bfloat16, 8),
+                                     (torch.bfloat16, 512)])
+def test_batch_smallest_and_widest_r(dtype, r):
+    """The narrowest rows of each storage type (one 16-byte vector: most lanes of a group
+    idle) and the widest a batch plan takes (64 lanes of 16 bytes): both schedules, staged
+    and unstaged tiles, bit-exact against the single-graph calls under the row-block schedule
+    and within the float32 gate of the oracle on the stored inputs."""
+    graphs, pats, A, B, G = _setup(dtype, nbatch=5, r=r, seed=98)
+    log(f"batch r={r} dtype={dtype}")
+    plan = F.BatchPlan(pats, A, B, G)
+    single = _single(pats, A, B, G)
+    for tile, rw, cw in ((2048, False, False), (8192, False, False), (2048, True, True)):
+        plan.set_schedule(tile_nnz=tile, placement=F.BatchPlan.PLACE_QUEUES, row_wave=rw, col_wave=cw)
+        for t in plan.C + plan.dA + plan.dB:
+            t.fill_(float("nan"))
+        plan.run()
+        torch.cuda.synchronize()
+        if not (rw or cw):
+            for k, (c, da, db) in enumerate(single):
+                assert torch.equal(plan.C[k], c) and torch.equal(plan.dA[k], da) and torch.equal(plan.dB[k], db), \
+                    (k, tile)
+        _check_oracle_stored(graphs, plan, dtype, f"r={r} tile={tile} rw={rw} cw={cw}")
+
+
+def _check_oracle_stored(graphs, plan, dtype, tag):
+    """Every graph against the oracle on the inputs as stored (bf16-rounded for bf16), at the
+    float32 gate."""
+    for k, g in enumerate(graphs):
+        S, Aq, Bq = g["S"], g["A"], g["B"]
+        if dtype == torch.bfloat16:
+            Aq, Bq = oracle.bf16_round(Aq), oracle.bf16_round(Bq)
+        ref, mag = ref_fusedmm_a(S, Aq, Bq)
+        gate(f"{tag} graph {k} C", host(plan.C[k]), ref, mag, TOL_F32)
+        dA, dB, mA, mB = ref_fusedmm_a_backward(S, Aq, Bq, g["G"])
+        gate(f"{tag} graph {k} dA", host(plan.dA[k]), dA, mA, TOL_F32)
+        gate(f"{tag} graph {k} dB", host(plan.dB[k]), dB, mB, TOL_F32)
