@@ -405,7 +405,9 @@ fmm_status fmm_batch_run(fmm_batch_plan *p, hipStream_t stream)
 fmm_status fmm_batch_autotune(fmm_batch_plan *p, hipStream_t stream)
 {
     if (!p) return FMM_ERR_NULL;
-    const int32_t tiles_opts[3] = {2048, 8192, 32768};
+    // tiles up to 2560 entries keep their operands in LDS for lines of up to 256 entries
+    const int32_t tiles_opts[4] = {1536, 2560, 8192, 32768};
+    const int n_tiles_opts = 4;
     const bool row_pass = true;  // forward or dA pass is always present
     const bool col_pass = (p->flags & FMM_BATCH_BWD) != 0;
     const int wave_opts = p->L < 64 ? 2 : 1;  // at L = 64 both schedules coincide
@@ -416,7 +418,7 @@ fmm_status fmm_batch_autotune(fmm_batch_plan *p, hipStream_t stream)
     int32_t bt = p->tile_nnz, bx = p->xcd, brw = p->rw, bcw = p->cw;
     int32_t count = 0;
     fmm_status st = FMM_OK;
-    for (int ti = 0; ti < 3 && st == FMM_OK; ++ti) {
+    for (int ti = 0; ti < n_tiles_opts && st == FMM_OK; ++ti) {
         for (int x = FMM_BATCH_PLACE_QUEUES; x >= FMM_BATCH_PLACE_GLOBAL && st == FMM_OK; --x) {
             for (int rw = 0; rw < (row_pass ? wave_opts : 1) && st == FMM_OK; ++rw) {
                 for (int cw = 0; cw < (col_pass ? wave_opts : 1) && st == FMM_OK; ++cw) {
