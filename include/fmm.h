@@ -585,7 +585,10 @@ fmm_status fmm_sddmm_residual(const fmm_sparse *S_csr, const void *A, const void
  *
  * The plan cuts every graph's lines into tiles of about tile_nnz stored entries,
  * assigns tiles to a fixed grid of workgroups (one resident wave set per CU) and keeps
- * the per-graph descriptor and tile tables in device memory it owns.  Schedules:
+ * the per-graph descriptor and tile tables in device memory it owns.  A workgroup copies
+ * the column indices and weights of a tile of at most 2816 stored entries into LDS once,
+ * so its batches read them there (same values, same results); larger tiles read them
+ * from memory.  Schedules:
  *   - row-block: L lanes per line, several lines per wave;
  *   - wavefront-per-line: the 64 lanes of a wave share one line, each lane group
  *     taking every (64/L)-th batch of entries, partial sums added across groups;
